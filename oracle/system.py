@@ -1,0 +1,180 @@
+"""The final-system operator of the array (section V eq. MV_product1, section III).
+
+    y = (D - G T A^-1 B) x,  with G applied by AIM:  G u ~= v(u) + C u,
+where T A^-1 B is block diagonal with one dense block M_t per distinct element
+(section III: computed once per distinct element and reused), D is block diagonal
+with one sparse block per equivalent surface (section IV), v(u) is the grid far
+field of section V steps (i)-(iii) and C is the pre-corrected near-field matrix.
+
+Unknowns are element-major: index m * n_rwg + n with m = iy * px + ix.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from synth import Workload
+
+from . import aim
+from .galerkin import efie_pairs
+from .geometry import rwg_geometry
+
+
+class OracleOperator:
+    def __init__(self, wl: Workload, near_mode: str = "offset", g0: complex = 0.0, pad=None,
+                 M: np.ndarray | None = None):
+        self.wl = wl
+        mesh = wl.surface
+        self.geo = rwg_geometry(mesh.vert, mesh.tri, mesh.rwg)
+        self.nb = self.geo.n_rwg
+        self.s_local, self.W = aim.projection_weights(self.geo, wl.h, wl.order)
+        self.offsets = wl.elem_offset_cells()
+        self.grid = aim.build_grid(self.s_local, self.offsets, wl.order)
+        self.Gs = aim.green_samples(self.grid.shape, wl.h, wl.k, g0)
+        self.pad = pad
+        self.M = wl.macromodels() if M is None else M
+        r, c, v = wl.d_matrix()
+        self.D = sp.csr_matrix((v, (r, c)), shape=(self.nb, self.nb))
+        self.near_mode = near_mode
+        self._build_near()
+
+    # ---- near field -------------------------------------------------------------
+    def _near_block(self, shift_a, ga, shift_b, gb):
+        """Near mask and pre-corrected values between two elements (absolute placement)."""
+        wl, geo = self.wl, self.geo
+        ca = geo.center + shift_a
+        cb = geo.center + shift_b
+        mask = aim.near_pairs(ca, ga, cb, gb, wl.r_near, wl.order)
+        a, b = np.nonzero(mask)
+        if a.size == 0:
+            return a, b, np.zeros(0, dtype=np.complex128)
+        exact = efie_pairs(geo, shift_a, a, geo, shift_b, b, wl.k, wl.eta)
+        grid = aim.grid_pair_values(self.W[:, a], ga[a], self.W[:, b], gb[b], self.Gs,
+                                    self.grid.shape, wl.k, wl.eta)
+        return a, b, exact - grid
+
+    def _build_near(self):
+        wl, nb = self.wl, self.nb
+        ne = wl.n_elem
+        gl = self.grid.g.reshape(ne, nb, 3)
+        centers = wl.elem_center()
+        ix = np.arange(ne) % wl.px
+        iy = np.arange(ne) // wl.px
+        rows, cols, vals = [], [], []
+        if self.near_mode == "global":
+            for m in range(ne):
+                for mp in range(ne):
+                    if max(abs(ix[m] - ix[mp]), abs(iy[m] - iy[mp])) > 2:
+                        continue
+                    a, b, v = self._near_block(centers[m], gl[m], centers[mp], gl[mp])
+                    rows.append(m * nb + a)
+                    cols.append(mp * nb + b)
+                    vals.append(v)
+        elif self.near_mode == "offset":
+            # translation invariance: one block per lattice offset, computed in local frame
+            self.blocks = {}
+            for dy in range(-min(2, wl.py - 1), min(2, wl.py - 1) + 1):
+                for dx in range(-min(2, wl.px - 1), min(2, wl.px - 1) + 1):
+                    sh = np.array([dx, dy, 0]) * wl.pitch_cells
+                    a, b, v = self._near_block(np.zeros(3), self.s_local, sh * wl.h, self.s_local + sh)
+                    if a.size:
+                        self.blocks[(dx, dy)] = (a, b, v)
+            for (dx, dy), (a, b, v) in self.blocks.items():
+                if ne * nb > 200_000:
+                    break  # large arrays use the per-offset blocks row by row
+                for m in range(ne):
+                    jx, jy = ix[m] + dx, iy[m] + dy
+                    if 0 <= jx < wl.px and 0 <= jy < wl.py:
+                        mp = jy * wl.px + jx
+                        rows.append(m * nb + a)
+                        cols.append(mp * nb + b)
+                        vals.append(v)
+        else:
+            raise ValueError(self.near_mode)
+        self._rows, self._cols, self._vals = rows, cols, vals
+        self._C = None
+
+    @property
+    def C(self):
+        """The pre-corrected near-field matrix as one global CSR (built on first use)."""
+        if self._C is None:
+            n = self.wl.n_elem * self.nb
+            self._C = sp.csr_matrix((np.concatenate(self._vals),
+                                     (np.concatenate(self._rows), np.concatenate(self._cols))),
+                                    shape=(n, n))
+        return self._C
+
+    # ---- products ---------------------------------------------------------------
+    def macro_apply(self, x: np.ndarray) -> np.ndarray:
+        """u_m = M_{t(m)} x_m for every element (section III, block-diagonal T A^-1 B)."""
+        nb, t = self.nb, self.wl.elem_type
+        X = x.reshape(-1, nb)
+        U = np.empty_like(X)
+        for m in range(X.shape[0]):
+            U[m] = self.M[t[m]] @ X[m]
+        return U.reshape(-1)
+
+    def far_field(self, u: np.ndarray, direct: bool = False) -> np.ndarray:
+        """v = sum_psi I_psi H_psi P_psi u (section V steps (i)-(iii))."""
+        Q = aim.project(self.grid, self.W, u)
+        Phi = aim.convolve_direct(Q, self.Gs) if direct else aim.convolve_fft(Q, self.Gs, self.pad)
+        return aim.interpolate(self.grid, self.W, Phi, self.wl.k, self.wl.eta)
+
+    def g_apply(self, u: np.ndarray, direct: bool = False) -> np.ndarray:
+        """G u ~= v + C u."""
+        return self.far_field(u, direct) + self.C @ u
+
+    def d_apply(self, x: np.ndarray) -> np.ndarray:
+        nb = self.nb
+        return (self.D @ x.reshape(-1, nb).T).T.reshape(-1)
+
+    def matvec(self, x: np.ndarray, direct: bool = False) -> np.ndarray:
+        """y = D x - G (M x) for one vector or a stack (R, n)."""
+        if x.ndim == 2:
+            return np.stack([self.matvec(xi, direct) for xi in x])
+        return self.d_apply(x) - self.g_apply(self.macro_apply(x), direct)
+
+    def dense(self) -> np.ndarray:
+        """The operator as a dense matrix, column by column (tiny arrays only)."""
+        n = self.wl.n_unknowns
+        out = np.empty((n, n), dtype=np.complex128)
+        e = np.zeros(n, dtype=np.complex128)
+        for j in range(n):
+            e[:] = 0
+            e[j] = 1
+            out[:, j] = self.matvec(e)
+        return out
+
+    def matvec_rows(self, x: np.ndarray, rows: np.ndarray) -> np.ndarray:
+        """y[rows] of y = D x - G (M x), for arrays too large for a global near matrix.
+
+        Uses the per-offset near blocks (translation invariance, pinned against the
+        global construction on small arrays) and the full grid far field.
+        """
+        if self.near_mode != "offset":
+            raise ValueError("matvec_rows needs near_mode='offset'")
+        wl, nb = self.wl, self.nb
+        rows = np.asarray(rows, dtype=np.int64)
+        u = self.macro_apply(x)
+        v = self.far_field_rows(u, rows)
+        X = x.reshape(-1, nb)
+        U = u.reshape(-1, nb)
+        out = np.empty(rows.size, dtype=np.complex128)
+        Dd = self.D.tocsr()
+        for i, gidx in enumerate(rows):
+            m, a = divmod(int(gidx), nb)
+            ix, iy = m % wl.px, m // wl.px
+            acc = Dd[a] @ X[m]
+            near = 0.0
+            for (dx, dy), (ba, bb, bv) in self.blocks.items():
+                jx, jy = ix + dx, iy + dy
+                if 0 <= jx < wl.px and 0 <= jy < wl.py:
+                    sel = ba == a
+                    near = near + np.sum(bv[sel] * U[jy * wl.px + jx, bb[sel]])
+            out[i] = acc[0] - (v[i] + near)
+        return out
+
+    def far_field_rows(self, u: np.ndarray, rows: np.ndarray) -> np.ndarray:
+        Q = aim.project(self.grid, self.W, u)
+        Phi = aim.convolve_fft(Q, self.Gs, self.pad)
+        return aim.interpolate_rows(self.grid, self.W, Phi, self.wl.k, self.wl.eta, rows)

@@ -1,0 +1,133 @@
+"""Structured triangle meshes and RWG edge tables (geometry and topology only).
+
+This module builds the discretisation that the method starts from (section II-A:
+RWG functions on the equivalent box surface), but it evaluates no basis function,
+integral or operator: it only produces vertex coordinates, triangle vertex lists
+and, for every interior edge, the pair of triangles that share it.
+
+Conventions shared by every consumer of these tables:
+  * lengths are in wavelengths, each element is centred at its own origin;
+  * triangles are listed counter-clockwise seen from outside the closed surface
+    (their right-hand normal points outwards);
+  * a unit square of a face, with corners P(i,j) in the face's (u, v) frame, is
+    split along the diagonal P(i,j)-P(i+1,j+1) into (P00, P10, P11) and
+    (P00, P11, P01);
+  * an RWG row is (v_a, v_b, T+, T-): the edge's end vertices with v_a < v_b, and
+    the two triangles sharing that edge with T+ < T-.  Rows are sorted by
+    (v_a, v_b).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class SurfaceMesh:
+    vert: np.ndarray  # (n_vert, 3) float64
+    tri: np.ndarray   # (n_tri, 3) int32
+    rwg: np.ndarray   # (n_rwg, 4) int32: v_a, v_b, T+, T-
+
+    @property
+    def n_vert(self) -> int:
+        return int(self.vert.shape[0])
+
+    @property
+    def n_tri(self) -> int:
+        return int(self.tri.shape[0])
+
+    @property
+    def n_rwg(self) -> int:
+        return int(self.rwg.shape[0])
+
+
+def rwg_table(tri: np.ndarray) -> np.ndarray:
+    """Interior edges of a triangle list as (v_a, v_b, T+, T-) rows.
+
+    Edges with a single adjacent triangle (open boundary) carry no RWG function.
+    An edge shared by more than two triangles is rejected (non-manifold).
+    """
+    owners: dict[tuple[int, int], list[int]] = {}
+    for t, (a, b, c) in enumerate(np.asarray(tri, dtype=np.int64)):
+        for u, v in ((a, b), (b, c), (c, a)):
+            key = (int(min(u, v)), int(max(u, v)))
+            owners.setdefault(key, []).append(t)
+    rows = []
+    for key in sorted(owners):
+        ts = owners[key]
+        if len(ts) == 1:
+            continue
+        if len(ts) != 2:
+            raise ValueError(f"non-manifold edge {key} shared by {len(ts)} triangles")
+        rows.append((key[0], key[1], min(ts), max(ts)))
+    return np.asarray(rows, dtype=np.int32).reshape(-1, 4)
+
+
+def cube_surface(side: float, n: int) -> SurfaceMesh:
+    """Closed surface of an axis-aligned cube of the given side, n x n squares per face.
+
+    Vertices are shared between faces, so the surface is closed and every edge is
+    interior: 6 n^2 + 2 vertices, 12 n^2 triangles, 18 n^2 RWG functions.
+    """
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    index: dict[tuple[int, int, int], int] = {}
+    verts: list[tuple[float, float, float]] = []
+
+    def vid(i: int, j: int, k: int) -> int:
+        key = (i, j, k)
+        if key not in index:
+            index[key] = len(verts)
+            verts.append(tuple(-0.5 * side + side * q / n for q in key))
+        return index[key]
+
+    # (fixed axis, fixed value, u axis, v axis) with u x v along the outward normal.
+    faces = (
+        (0, n, 1, 2), (0, 0, 2, 1),
+        (1, n, 2, 0), (1, 0, 0, 2),
+        (2, n, 0, 1), (2, 0, 1, 0),
+    )
+    tris: list[tuple[int, int, int]] = []
+    for fixed, val, ua, va in faces:
+        def P(i: int, j: int) -> int:
+            c = [0, 0, 0]
+            c[fixed] = val
+            c[ua] = i
+            c[va] = j
+            return vid(*c)
+        for j in range(n):
+            for i in range(n):
+                p00, p10, p11, p01 = P(i, j), P(i + 1, j), P(i + 1, j + 1), P(i, j + 1)
+                tris.append((p00, p10, p11))
+                tris.append((p00, p11, p01))
+    tri = np.asarray(tris, dtype=np.int32)
+    return SurfaceMesh(np.asarray(verts, dtype=np.float64), tri, rwg_table(tri))
+
+
+def square_plate(side: float, n: int, z: float = 0.0) -> SurfaceMesh:
+    """Zero-thickness square plate in the plane z, n x n squares, normal +z."""
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    g = -0.5 * side + side * np.arange(n + 1) / n
+    vert = np.array([(g[i], g[j], z) for j in range(n + 1) for i in range(n + 1)], dtype=np.float64)
+
+    def P(i: int, j: int) -> int:
+        return j * (n + 1) + i
+
+    tris = []
+    for j in range(n):
+        for i in range(n):
+            tris.append((P(i, j), P(i + 1, j), P(i + 1, j + 1)))
+            tris.append((P(i, j), P(i + 1, j + 1), P(i, j + 1)))
+    tri = np.asarray(tris, dtype=np.int32)
+    return SurfaceMesh(vert, tri, rwg_table(tri))
+
+
+def vertex_triangles(mesh: SurfaceMesh) -> list[list[int]]:
+    """For every vertex, the triangles that contain it (topology only)."""
+    out: list[list[int]] = [[] for _ in range(mesh.n_vert)]
+    for t, row in enumerate(mesh.tri):
+        for v in row:
+            out[int(v)].append(t)
+    return out
