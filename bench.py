@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Benchmark of the solve-time path on one MI355X.
+
+Workload: 32 x 32 array of Jerusalem-cross elements in 0.55-wavelength equivalent
+boxes (6 x 6 squares per face, 648 RWG per box, 663,552 unknowns), AIM grid
+h = 0.1 wavelength, order 2 (195 x 195 x 9 nodes, FFT lengths 400 x 400), one
+plane wave at theta = 30 deg, phi = 45 deg.  Seeded synthetic data (see synth/).
+
+One step = one GMRES(50) solve to 1e-6 relative residual in mixed precision
+(complex FP32 products and basis, FP64 Gram-Schmidt sums, Hessenberg, Givens and
+a FP64 residual product at every restart).  `value` = AIM matrix-vector products
+per second over the timed solves (every product counts, FP64 restart products
+included).  The FP64 solve, the standalone products, per-kernel times and the
+oracle's CPU rate are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 157.3
+FP64_VALU_PEAK_TFLOPS = 78.6
+METRIC = "AIM matvecs/s and solve time to 1e-6 residual, mixed vs FP64; p50/p99 latency"
+
+
+def kernel_model(info: dict, R: int, bytes_per: int) -> dict:
+    """Algorithmic HBM bytes (or flops for the GEMM) per launch of each kernel."""
+    nx, ny, nz, lx, ly = info["nx"], info["ny"], info["nz"], info["lx"], info["ly"]
+    n = info["n_rwg"] * info["n_elem"]
+    grid = 4 * R * nx * ny * nz * bytes_per
+    spec = 4 * R * nx * ly * nz * bytes_per
+    gt = (lx // 2 + 1) * (ly // 2 + 1) * nz * bytes_per
+    vec = n * R * bytes_per
+    return {
+        "macro_gemm": {"flops": 8.0 * info["n_rwg"] ** 2 * info["n_elem"] * R, "bytes": 2 * vec},
+        "project": {"bytes": vec + grid},
+        "fft_y_fwd": {"bytes": grid + spec},
+        "fft_x_conv": {"bytes": 2 * spec + gt},
+        "fft_y_inv": {"bytes": spec + grid},
+        "interp_near_d": {"bytes": grid + 3 * vec},
+    }
+
+
+def cpu_baseline(wl, budget_s: float = 20.0) -> dict:
+    """The CPU oracle's full product on the same workload, single thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle.system import OracleOperator
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        op = OracleOperator(wl)
+        setup = time.perf_counter() - t0
+        x = wl.test_vectors(1)[0]
+        times = []
+        t_start = time.perf_counter()
+        while True:
+            t = time.perf_counter()
+            op.matvec(x)
+            times.append(time.perf_counter() - t)
+            if time.perf_counter() - t_start > budget_s * 0.5 or len(times) >= 5:
+                break
+    per = float(np.median(times))
+    return {"value": 1.0 / per, "unit": "matvecs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(times)} full FP64 products of the same 663,552-unknown workload "
+                      f"(median {per:.2f} s each; {setup:.1f} s untimed setup), numpy/scipy, 1 thread"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--restart", type=int, default=50)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solves")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the path shards over right-hand sides or x-slabs, see DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1712_02443_amd import AIM_FP64, AIM_MIXED, AimOperator
+    from synth import make_workload
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    wl = make_workload(1)
+    print(f"[bench] building {wl.name}: {wl.n_unknowns} unknowns", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    op = AimOperator.from_workload(wl)
+    op.set_macromodels(wl.macromodels())
+    op.set_dmatrix(*wl.d_matrix())
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    info = op.info()
+    b = op.plane_wave_rhs(wl.theta, wl.phi, wl.pol)
+    solve_kw = dict(restart=args.restart, tol=args.tol, max_iters=5000)
+
+    def solve(prec):
+        x, st, code = op.gmres(b, precision=prec, **solve_kw)
+        return st[0], code
+
+    for _ in range(args.warmup):
+        solve(AIM_MIXED)
+    print("[bench] warm-up done", file=sys.stderr, flush=True)
+
+    # timed region: exactly `steps` mixed-precision solves
+    lat = []
+    matvecs = 0
+    stats = None
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        t = time.perf_counter()
+        stats, code = solve(AIM_MIXED)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t)
+        matvecs += stats["matvecs"]
+        if code != 0:
+            print(f"[bench] mixed solve did not converge: {stats}", file=sys.stderr)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    value = matvecs / elapsed
+    print(f"[bench] mixed: {elapsed / args.steps * 1e3:.2f} ms/solve, {stats}", file=sys.stderr, flush=True)
+
+    out = {}
+    if not args.no_fp64:
+        solve(AIM_FP64)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        mv64 = 0
+        for _ in range(args.steps):
+            st64, _ = solve(AIM_FP64)
+            mv64 += st64["matvecs"]
+        torch.cuda.synchronize()
+        e64 = time.perf_counter() - t
+        out["fp64_solve_ms"] = e64 / args.steps * 1e3
+        out["fp64_matvecs_per_s"] = mv64 / e64
+        out["fp64_iters"] = st64["iters"]
+        out["fp64_true_relres"] = st64["true_relres"]
+        out["mixed_vs_fp64_solve_speedup"] = (e64 / args.steps) / (elapsed / args.steps)
+        print(f"[bench] fp64: {out['fp64_solve_ms']:.2f} ms/solve, {st64}", file=sys.stderr, flush=True)
+
+    # standalone products
+    x64 = torch.from_numpy(wl.test_vectors(1)).to("cuda")
+    x32 = x64.to(torch.complex64)
+    for name, xv, prec in (("product_fp32_us", x32, AIM_MIXED), ("product_fp64_us", x64, AIM_FP64)):
+        y = torch.empty_like(xv)
+        for _ in range(3):
+            op.matvec(xv, precision=prec, out=y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.kernel_reps):
+            op.matvec(xv, precision=prec, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / args.kernel_reps * 1e3
+
+    # per-kernel times of the mixed product, roofline of the dominant kernel
+    kt = op.time_kernels(x32, precision=AIM_MIXED, reps=args.kernel_reps)
+    kt64 = op.time_kernels(x64, precision=AIM_FP64, reps=args.kernel_reps)
+    model = kernel_model(info, 1, 8)
+    dom = max(kt, key=kt.get)
+    if "flops" in model[dom]:
+        ach = model[dom]["flops"] / (kt[dom] * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP32_VALU_PEAK_TFLOPS, "traffic": None}
+    else:
+        ach = model[dom]["bytes"] / (kt[dom] * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None}
+    per_kernel = {}
+    for k, ms in kt.items():
+        m = model[k]
+        ent = {"us": ms * 1e3}
+        if "flops" in m:
+            ent["tflops"] = m["flops"] / (ms * 1e-3) / 1e12
+        else:
+            ent["gbs"] = m["bytes"] / (ms * 1e-3) / 1e9
+        per_kernel[k] = ent
+    out["kernels_fp32"] = per_kernel
+    out["kernels_fp64_us"] = {k: v * 1e3 for k, v in kt64.items()}
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 products + f64 Krylov sums",
+        "data": "synthetic (seeded meshes, macromodel blocks and D; plane-wave excitation)",
+        "config": {"workload": "jc-32x32-mixed: 32x32 array, 648 RWG/box, 663552 unknowns, grid 195x195x9, "
+                               "FFT 400x400, 1 RHS, GMRES(50) to 1e-6",
+                   "unknowns": wl.n_unknowns, "nrhs": 1, "restart": args.restart, "tol": args.tol},
+        "solve_ms_p50": float(np.percentile(lat, 50) * 1e3),
+        "solve_ms_p99": float(np.percentile(lat, 99) * 1e3),
+        "iters": stats["iters"], "restarts": stats["restarts"], "matvecs_per_solve": stats["matvecs"],
+        "true_relres": stats["true_relres"],
+        "build_s": build_s,
+        "roofline": roof,
+    }
+    line.update(out)
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(wl)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,209 @@
+/*
+ * aimm: the solve-time path of the macromodel surface-integral-equation method for
+ * large arrays of scatterers (Patel, Triverio, Hum, arXiv:1712.02443), on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library solves the final system of section IV, eq. finalsystem,
+ *     (D - G T A^-1 B) E = V,
+ * by GMRES (section V), and applies its matrix-vector product, eq. MV_product1,
+ *     y = (D - G T A^-1 B) x,
+ * with G accelerated by the adaptive integral method (section V, steps (i)-(iii)).
+ *
+ * Model of the problem (section III): an array of px x py elements on a square
+ * lattice, every element enclosed by the same closed equivalent surface (one RWG
+ * mesh, N RWG functions), each element of one of n_types distinct kinds.  The block
+ * T_m A_m^-1 B_m is shared by all elements of one kind (section III: computed once
+ * per distinct element) and is given to the library as one dense N x N block M_t.
+ * D is block diagonal with one sparse N x N block shared by all elements (the
+ * surface is the same for all of them).  The library computes everything else:
+ * AIM stencils and projection weights, the Green's-function spectrum, the exact
+ * near-field Galerkin entries of eq. Gouter1 and their pre-correction.
+ *
+ * Conventions
+ *   - Complex numbers are interleaved (re, im).  AIM_FP64 data is complex128,
+ *     AIM_MIXED data is complex64.  Right-hand sides and solutions of gmres_solve
+ *     are always complex128.
+ *   - Unknowns are element-major: index r * (n_elem * N) + m * N + n for right-hand
+ *     side r, element m = iy * px + ix, RWG function n.
+ *   - Lengths are in wavelengths; element m is centred at (pitch_cells * h * ix,
+ *     pitch_cells * h * iy, 0); the surface mesh is given in element-local
+ *     coordinates.
+ *   - Pointers named "device" must be device memory owned by the caller; the
+ *     library never frees them.  Host pointers are read during the call only.
+ *   - Streams are hipStream_t passed as void* (NULL = the null stream).  One op is
+ *     used by one stream at a time; calls on different ops may overlap.
+ *   - Every entry point returns an aim_status.  On AIM_EINVAL no output is
+ *     touched; aim_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef AIMM_H
+#define AIMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct aim_op aim_op;
+
+enum aim_status {
+  AIM_OK = 0,
+  AIM_ENOCONV = 1,   /* gmres_solve: some right-hand side did not reach tol */
+  AIM_EINVAL = -1,   /* bad argument; nothing was modified */
+  AIM_ENOMEM = -2,   /* device allocation failed */
+  AIM_EDEVICE = -3,  /* a HIP call or kernel launch failed */
+  AIM_ESTATE = -4    /* operator data missing (macromodels or D not set) */
+};
+
+enum aim_precision {
+  AIM_FP64 = 0,  /* every step in complex FP64 */
+  AIM_MIXED = 1  /* complex FP32 storage and arithmetic for the product */
+};
+
+enum aim_matvec_flags {
+  AIM_FULL = 0,      /* y = D x - G (M x)                                  */
+  AIM_G_ONLY = 1,    /* y = G x: AIM far field plus pre-corrected near field */
+  AIM_FAR_ONLY = 2   /* y = sum_psi I_psi H_psi P_psi x (grid part only)     */
+};
+
+/* One closed equivalent surface in element-local coordinates (section II-A). */
+typedef struct {
+  int32_t n_vert, n_tri, n_rwg;
+  const double* vert;   /* host [n_vert][3] */
+  const int32_t* tri;   /* host [n_tri][3], counter-clockwise seen from outside */
+  const int32_t* rwg;   /* host [n_rwg][4] = v_a, v_b (the edge), T+, T- */
+} aim_surface;
+
+/* The array and the AIM parameters (sections III and V). */
+typedef struct {
+  double k;             /* wavenumber (2 pi in wavelength units) */
+  double eta;           /* free-space impedance */
+  double h;             /* AIM grid spacing */
+  double r_near;        /* near-field radius between RWG edge midpoints */
+  int32_t order;        /* stencil order N_O (N_O + 1 nodes per axis), 1..3 */
+  int32_t px, py;       /* lattice size */
+  int32_t pitch_cells;  /* lattice pitch in grid cells */
+  int32_t n_types;      /* number of distinct elements */
+  const int32_t* elem_type;  /* host [py*px], values in [0, n_types) */
+  int32_t max_rhs;      /* largest right-hand-side count any call will use */
+} aim_array;
+
+typedef struct {
+  int32_t n_rwg, n_elem, n_types;
+  int32_t nx, ny, nz;          /* unpadded AIM grid (nodes) */
+  int32_t lx, ly;              /* padded FFT lengths along x and y */
+  int32_t n_offsets;           /* lattice offsets with near-field pairs */
+  int64_t near_nnz;            /* pre-corrected near-field entries per element row block */
+  int64_t d_nnz;               /* entries of the D block (0 until set) */
+  int64_t device_bytes;        /* device memory held by the op */
+} aim_info;
+
+/* Build the AIM operator of section V for the array: stencils, projection and
+ * interpolation weights, FFT plan and Green's-function spectrum (on the device),
+ * and the pre-corrected near field (exact entries of eq. Gouter1 on near pairs minus
+ * their grid approximation).  Allocates device memory for max_rhs right-hand sides.
+ * Uses the current HIP device.  *out is set only on success. */
+int aim_build_grid(const aim_surface* surface, const aim_array* array, aim_op** out);
+
+/* The host part of aim_build_grid alone: stencils, weights and the pre-corrected
+ * near field, with no device call.  The op serves aim_get_info and aim_get_near;
+ * every device entry point returns AIM_ESTATE on it.  For inspection and tests on
+ * hosts without a GPU. */
+int aim_build_host(const aim_surface* surface, const aim_array* array, aim_op** out);
+
+/* Per-kind block M_t = T_t A_t^-1 B_t (section III, eq. Tm1 and eq. JABE), host
+ * complex128 [n_types][N][N], column-major within each block.  Copied. */
+int aim_set_macromodels(aim_op* op, const double* M);
+
+/* The sparse block D_m (section IV) shared by all elements, as host coordinate
+ * lists: rows[nnz], cols[nnz] in [0, N), vals complex128 [nnz].  Copied. */
+int aim_set_dmatrix(aim_op* op, int64_t nnz, const int32_t* rows, const int32_t* cols,
+                    const double* vals);
+
+/* u = blockdiag(M_t(m)) x for nrhs right-hand sides (section III).  x, u: device. */
+int macro_apply(aim_op* op, const void* x, void* u, int32_t nrhs, int32_t precision,
+                void* stream);
+
+/* The product of eq. MV_product1, or a part of it (see aim_matvec_flags).
+ * x, y: device, nrhs <= max_rhs.  No allocation and no host synchronisation. */
+int aim_matvec(aim_op* op, const void* x, void* y, int32_t nrhs, int32_t precision,
+               int32_t flags, void* stream);
+
+/* Kernel timing of the full product with HIP events on `stream`: one warm-up, then
+ * reps products; ms[k] receives the mean duration in milliseconds of kernel k:
+ * 0 macromodel GEMM, 1 projection (step (i)), 2 forward FFT along y, 3 FFT along x
+ * with the kernel-spectrum product, 4 inverse FFT along y (steps (ii)), 5
+ * interpolation (step (iii)) fused with the near field and D.  ms: host [6].
+ * Synchronises the stream. */
+int aim_time_kernels(aim_op* op, const void* x, void* y, int32_t nrhs, int32_t precision,
+                     int32_t reps, double* ms, void* stream);
+
+/* Step (i) alone: grid charges and currents Q[r][psi][x][y][z] (psi = x, y, z, phi)
+ * on the unpadded grid.  u: device vector, Q: device [nrhs][4][nx][ny][nz]. */
+int aim_project(aim_op* op, const void* u, void* Q, int32_t nrhs, int32_t precision,
+                void* stream);
+
+/* Step (ii) alone: grid potentials Phi = H Q (aperiodic convolution with the sampled
+ * Green's function).  Q and Phi: device [nrhs][4][nx][ny][nz]; may alias. */
+int aim_convolve(aim_op* op, const void* Q, void* Phi, int32_t nrhs, int32_t precision,
+                 void* stream);
+
+/* Plane-wave excitation of eq. V1, V_n = -<Lambda_n, E_inc>, for incidence angles
+ * (theta, phi) in radians and polarisation pol (0 = theta-hat, 1 = phi-hat).
+ * theta, phi, pol: host [nrhs].  b: device complex128. */
+int aim_plane_wave_rhs(aim_op* op, const double* theta, const double* phi, const int32_t* pol,
+                       int32_t nrhs, void* b, void* stream);
+
+typedef struct {
+  int32_t restart;      /* Krylov dimension per cycle (GMRES(m)) */
+  int32_t max_iters;    /* total inner iterations per right-hand side */
+  int32_t precision;    /* AIM_FP64: all FP64.  AIM_MIXED: inner cycles with FP32
+                           products and FP32 basis storage, FP64 dot products,
+                           Hessenberg and Givens; FP64 residual at every restart */
+  int32_t x0_given;     /* 0: start from x = 0; 1: start from the x passed in */
+  int32_t check_every;  /* iterations between host convergence checks (>= 1) */
+  double tol;           /* relative residual target ||b - A x|| / ||b|| */
+} gmres_opts;
+
+typedef struct {
+  int32_t iters;        /* inner iterations */
+  int32_t restarts;     /* completed cycles */
+  int32_t converged;    /* 1 if the FP64 true relative residual <= tol */
+  int32_t matvecs;      /* products applied to this right-hand side */
+  double true_relres;   /* final FP64 true relative residual */
+} gmres_stat;
+
+/* Solve eq. finalsystem for nrhs right-hand sides with restarted GMRES (section V),
+ * one independent Krylov space per right-hand side.  b, x: device complex128
+ * [nrhs][n_unknowns]; stats: host [nrhs].  Returns AIM_ENOCONV (and the last
+ * iterate in x) if a right-hand side misses tol within max_iters.  Allocates the
+ * Krylov basis on first use and keeps it with the op. */
+int gmres_solve(aim_op* op, const void* b, void* x, int32_t nrhs, const gmres_opts* opts,
+                gmres_stat* stats, void* stream);
+
+/* Sizes of the op (host only, no device work). */
+int aim_get_info(const aim_op* op, aim_info* info);
+
+/* Copy the pre-corrected near-field entries (host outputs, each of length
+ * info.near_nnz): row n, offset index o, column n', complex128 value.  The offset
+ * (dx, dy) of index o is returned in offsets[2*o], offsets[2*o+1]. */
+int aim_get_near(const aim_op* op, int32_t* rows, int32_t* offs, int32_t* cols, double* vals,
+                 int32_t* offsets);
+
+/* Device bytes an op of this array would hold, Krylov basis included, for admission
+ * decisions; host only. */
+size_t aim_footprint_bytes(const aim_surface* surface, const aim_array* array, int32_t nrhs,
+                           int32_t restart, int32_t precision);
+
+/* Release every resource of the op (synchronises the device). NULL is ignored. */
+void aim_destroy(aim_op* op);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* aim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AIMM_H */

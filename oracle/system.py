@@ -120,9 +120,29 @@ class OracleOperator:
         Phi = aim.convolve_direct(Q, self.Gs) if direct else aim.convolve_fft(Q, self.Gs, self.pad)
         return aim.interpolate(self.grid, self.W, Phi, self.wl.k, self.wl.eta)
 
+    def near_apply(self, u: np.ndarray, by_blocks: bool | None = None) -> np.ndarray:
+        """C u; per-offset blocks for arrays too large for one global sparse matrix."""
+        wl, nb = self.wl, self.nb
+        if by_blocks is None:
+            by_blocks = self.near_mode == "offset" and wl.n_elem * nb > 200_000
+        if not by_blocks:
+            return self.C @ u
+        U = u.reshape(wl.py, wl.px, nb)
+        out = np.zeros_like(U)
+        for (dx, dy), (a, b, v) in self.blocks.items():
+            Co = sp.csr_matrix((v, (a, b)), shape=(nb, nb))
+            src = np.zeros_like(U)
+            ys = slice(max(0, dy), wl.py + min(0, dy))
+            xs = slice(max(0, dx), wl.px + min(0, dx))
+            yd = slice(max(0, -dy), wl.py - max(0, dy))
+            xd = slice(max(0, -dx), wl.px - max(0, dx))
+            src[yd, xd] = U[ys, xs]
+            out += (Co @ src.reshape(-1, nb).T).T.reshape(U.shape)
+        return out.reshape(-1)
+
     def g_apply(self, u: np.ndarray, direct: bool = False) -> np.ndarray:
         """G u ~= v + C u."""
-        return self.far_field(u, direct) + self.C @ u
+        return self.far_field(u, direct) + self.near_apply(u)
 
     def d_apply(self, x: np.ndarray) -> np.ndarray:
         nb = self.nb

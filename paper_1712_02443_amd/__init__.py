@@ -1,0 +1,179 @@
+"""MI355X-native solve-time path of the macromodel + AIM method (arXiv:1712.02443).
+
+`AimOperator` wraps one array problem held by libaimm.so: the AIM-accelerated
+final-system product (D - G T A^-1 B) x (section V, eq. MV_product1), its parts,
+the plane-wave excitation (eq. V1) and the restarted GMRES solve of
+eq. finalsystem.  Tensors must live on the GPU; complex128 for AIM_FP64 and
+complex64 for AIM_MIXED products, complex128 for solves.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (AIM_FAR_ONLY, AIM_FP64, AIM_FULL, AIM_G_ONLY, AIM_MIXED, AimError, GmresOpts, GmresStat,
+                   check, load)
+
+__all__ = ["AimOperator", "AIM_FP64", "AIM_MIXED", "AIM_FULL", "AIM_G_ONLY", "AIM_FAR_ONLY", "AimError",
+           "footprint_bytes", "load"]
+
+
+def _stream(torch, stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def footprint_bytes(vert, tri, rwg, *, k, eta, h, r_near, order, px, py, pitch_cells, elem_type, n_types,
+                    max_rhs, nrhs, restart, precision) -> int:
+    st = _lib.Structs(vert, tri, rwg, k, eta, h, r_near, order, px, py, pitch_cells, elem_type, n_types, max_rhs)
+    return int(load().aim_footprint_bytes(ctypes.byref(st.surface), ctypes.byref(st.array), nrhs, restart,
+                                          precision))
+
+
+class AimOperator:
+    """One array problem on the current GPU (see include/aimm.h for the conventions)."""
+
+    def __init__(self, vert, tri, rwg, *, k, eta, h, r_near, order, px, py, pitch_cells, elem_type, n_types,
+                 max_rhs=1, host_only=False):
+        self.lib = load()
+        self._op = None
+        self._st = _lib.Structs(vert, tri, rwg, k, eta, h, r_near, order, px, py, pitch_cells, elem_type,
+                                n_types, max_rhs)
+        if not host_only:
+            import torch
+            self._torch = torch
+        h_op = ctypes.c_void_p()
+        build = self.lib.aim_build_host if host_only else self.lib.aim_build_grid
+        check(build(ctypes.byref(self._st.surface), ctypes.byref(self._st.array), ctypes.byref(h_op)))
+        self._op = h_op
+        self.max_rhs = int(max_rhs)
+        inf = self.info()
+        self.n_rwg, self.n_elem = inf["n_rwg"], inf["n_elem"]
+        self.n = self.n_rwg * self.n_elem
+        self.grid = (inf["nx"], inf["ny"], inf["nz"])
+
+    @classmethod
+    def from_workload(cls, wl, max_rhs=None, host_only=False):
+        m = wl.surface
+        return cls(m.vert, m.tri, m.rwg, k=wl.k, eta=wl.eta, h=wl.h, r_near=wl.r_near, order=wl.order,
+                   px=wl.px, py=wl.py, pitch_cells=wl.pitch_cells, elem_type=wl.elem_type, n_types=wl.n_types,
+                   max_rhs=wl.nrhs if max_rhs is None else max_rhs, host_only=host_only)
+
+    def close(self):
+        if getattr(self, "_op", None):
+            self.lib.aim_destroy(self._op)
+            self._op = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- data ---------------------------------------------------------------------
+    def set_macromodels(self, M: np.ndarray):
+        """M: (n_types, N, N) complex; stored column-major as the library expects."""
+        Mc = np.ascontiguousarray(np.transpose(np.asarray(M, dtype=np.complex128), (0, 2, 1)))
+        check(self.lib.aim_set_macromodels(self._op, Mc.view(np.float64).ctypes.data_as(_lib._f64p)))
+        self._M = Mc
+
+    def set_dmatrix(self, rows, cols, vals):
+        r = np.ascontiguousarray(rows, dtype=np.int32)
+        c = np.ascontiguousarray(cols, dtype=np.int32)
+        v = np.ascontiguousarray(vals, dtype=np.complex128)
+        check(self.lib.aim_set_dmatrix(self._op, r.shape[0], r.ctypes.data_as(_lib._i32p),
+                                       c.ctypes.data_as(_lib._i32p), v.view(np.float64).ctypes.data_as(_lib._f64p)))
+
+    def info(self) -> dict:
+        inf = _lib.AimInfo()
+        check(self.lib.aim_get_info(self._op, ctypes.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in inf._fields_}
+
+    def near(self):
+        """Pre-corrected near field: rows, offset index, cols, values, offsets (dx, dy)."""
+        inf = self.info()
+        nnz = inf["near_nnz"]
+        rows = np.empty(nnz, np.int32)
+        offs = np.empty(nnz, np.int32)
+        cols = np.empty(nnz, np.int32)
+        vals = np.empty(nnz, np.complex128)
+        offsets = np.empty(2 * max(inf["n_offsets"], 1), np.int32)
+        check(self.lib.aim_get_near(self._op, rows.ctypes.data_as(_lib._i32p), offs.ctypes.data_as(_lib._i32p),
+                                    cols.ctypes.data_as(_lib._i32p), vals.view(np.float64).ctypes.data_as(_lib._f64p),
+                                    offsets.ctypes.data_as(_lib._i32p)))
+        return rows, offs, cols, vals, offsets[:2 * inf["n_offsets"]].reshape(-1, 2)
+
+    # ---- device work ------------------------------------------------------------------
+    def _check_vec(self, x, prec):
+        torch = self._torch
+        want = torch.complex128 if prec == AIM_FP64 else torch.complex64
+        if x.dtype != want or not x.is_cuda or not x.is_contiguous():
+            raise ValueError(f"expected a contiguous {want} CUDA tensor")
+        if x.numel() % self.n:
+            raise ValueError("tensor size is not a multiple of the unknown count")
+        return x.numel() // self.n
+
+    def matvec(self, x, precision=AIM_FP64, flags=AIM_FULL, out=None, stream=None):
+        R = self._check_vec(x, precision)
+        y = self._torch.empty_like(x) if out is None else out
+        check(self.lib.aim_matvec(self._op, _dev_ptr(x), _dev_ptr(y), R, precision, flags, _stream(self._torch, stream)))
+        return y
+
+    KERNELS = ("macro_gemm", "project", "fft_y_fwd", "fft_x_conv", "fft_y_inv", "interp_near_d")
+
+    def time_kernels(self, x, precision=AIM_FP64, reps=20, stream=None) -> dict:
+        """Mean per-kernel duration (ms) of the full product, from HIP events on the stream."""
+        R = self._check_vec(x, precision)
+        y = self._torch.empty_like(x)
+        ms = np.zeros(6)
+        check(self.lib.aim_time_kernels(self._op, _dev_ptr(x), _dev_ptr(y), R, precision, int(reps),
+                                        ms.ctypes.data_as(_lib._f64p), _stream(self._torch, stream)))
+        return dict(zip(self.KERNELS, ms.tolist()))
+
+    def macro_apply(self, x, precision=AIM_FP64, out=None, stream=None):
+        R = self._check_vec(x, precision)
+        u = self._torch.empty_like(x) if out is None else out
+        check(self.lib.macro_apply(self._op, _dev_ptr(x), _dev_ptr(u), R, precision, _stream(self._torch, stream)))
+        return u
+
+    def project(self, u, precision=AIM_FP64, stream=None):
+        R = self._check_vec(u, precision)
+        nx, ny, nz = self.grid
+        Q = self._torch.empty((R, 4, nx, ny, nz), dtype=u.dtype, device=u.device)
+        check(self.lib.aim_project(self._op, _dev_ptr(u), _dev_ptr(Q), R, precision, _stream(self._torch, stream)))
+        return Q
+
+    def convolve(self, Q, precision=AIM_FP64, stream=None):
+        R = Q.shape[0]
+        Phi = self._torch.empty_like(Q)
+        check(self.lib.aim_convolve(self._op, _dev_ptr(Q), _dev_ptr(Phi), R, precision, _stream(self._torch, stream)))
+        return Phi
+
+    def plane_wave_rhs(self, theta, phi, pol, stream=None):
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        ph = np.ascontiguousarray(phi, dtype=np.float64)
+        po = np.ascontiguousarray(pol, dtype=np.int32)
+        R = th.shape[0]
+        b = self._torch.empty((R, self.n), dtype=self._torch.complex128, device="cuda")
+        check(self.lib.aim_plane_wave_rhs(self._op, th.ctypes.data_as(_lib._f64p), ph.ctypes.data_as(_lib._f64p),
+                                          po.ctypes.data_as(_lib._i32p), R, _dev_ptr(b), _stream(self._torch, stream)))
+        return b
+
+    def gmres(self, b, x=None, *, restart=50, tol=1e-6, max_iters=1000, precision=AIM_FP64, check_every=1,
+              stream=None):
+        R = self._check_vec(b, AIM_FP64)
+        x0_given = x is not None
+        if x is None:
+            x = self._torch.empty_like(b)
+        opts = GmresOpts(int(restart), int(max_iters), int(precision), int(x0_given), int(check_every), float(tol))
+        stats = (GmresStat * R)()
+        code = check(self.lib.gmres_solve(self._op, _dev_ptr(b), _dev_ptr(x), R, ctypes.byref(opts), stats,
+                                          _stream(self._torch, stream)))
+        st = [{name: getattr(s, name) for name, _ in s._fields_} for s in stats]
+        return x, st, code

@@ -1,0 +1,731 @@
+// C ABI of the library: operator construction, the final-system product of
+// eq. MV_product1 and its parts.  GMRES lives in gmres.hip.
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/aimm.h"
+#include "op.hpp"
+
+namespace aimm {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+#define AIM_HIP(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t _e = (expr);                                                              \
+    if (_e != hipSuccess) {                                                              \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(_e));                      \
+      return AIM_EDEVICE;                                                                \
+    }                                                                                    \
+  } while (0)
+
+static FftPlan make_plan(int L, std::vector<int>& rev, std::vector<int>& pos) {
+  std::vector<int> f = radix_plan(L);
+  if (f.empty() || int(f.size()) > kMaxStages) throw std::invalid_argument("FFT length not 5-smooth");
+  FftPlan P{};
+  P.L = L;
+  P.nst = int(f.size());
+  int B = L;
+  for (int s = 0; s < P.nst; ++s) {
+    P.radix[s] = f[s];
+    P.stride[s] = B / f[s];
+    P.tw_step[s] = L / B;
+    B = P.stride[s];
+  }
+  rev.assign(L, 0);
+  pos.assign(L, 0);
+  for (int p = 0; p < L; ++p) {
+    int rem = p, k = 0, mult = 1;
+    for (int s = 0; s < P.nst; ++s) {
+      const int qd = rem / P.stride[s];
+      rem -= qd * P.stride[s];
+      k += qd * mult;
+      mult *= P.radix[s];
+    }
+    rev[p] = k;
+    pos[k] = p;
+  }
+  return P;
+}
+
+template <typename T>
+static void twiddles(int L, std::vector<cplx<T>>& out) {
+  out.resize(L);
+  for (int t = 0; t < L; ++t) {
+    const long double a = -2.0L * 3.141592653589793238462643383279502884L * (long double)t / (long double)L;
+    out[t].re = T(std::cos(a));
+    out[t].im = T(std::sin(a));
+  }
+}
+
+template <typename T>
+static T* upload(aim_op* op, const T* host, size_t n) {
+  T* d = op->mem.alloc<T>(n);
+  if (n && hipMemcpy(d, host, n * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    throw std::runtime_error("hipMemcpy upload failed");
+  return d;
+}
+
+template <typename T>
+static void fill_prec(aim_op* op, PrecData<T>& P) {
+  const Setup& st = op->st;
+  const int N = st.N, q3 = st.q3;
+  std::vector<T> Wp(st.W.size()), Wt(st.W.size());
+  for (int p = 0; p < 4; ++p)
+    for (int n = 0; n < N; ++n)
+      for (int s = 0; s < q3; ++s) {
+        const double w = st.W[(size_t(p) * N + n) * q3 + s];
+        Wp[(size_t(p) * N + n) * q3 + s] = T(w);
+        Wt[(size_t(p) * q3 + s) * N + n] = T(w);
+      }
+  P.Wp = upload(op, Wp.data(), Wp.size());
+  P.Wt = upload(op, Wt.data(), Wt.size());
+  std::vector<cplx<T>> nv(st.near_val.size());
+  for (size_t i = 0; i < nv.size(); ++i) {
+    nv[i].re = T(st.near_val[i].real());
+    nv[i].im = T(st.near_val[i].imag());
+  }
+  P.near = upload(op, nv.data(), nv.size());
+  std::vector<cplx<T>> tw;
+  twiddles<T>(op->Lx, tw);
+  P.tw_x = upload(op, tw.data(), tw.size());
+  twiddles<T>(op->Ly, tw);
+  P.tw_y = upload(op, tw.data(), tw.size());
+  P.gt = op->mem.alloc<cplx<T>>(size_t(op->Lx / 2 + 1) * (op->Ly / 2 + 1) * st.nz);
+  // ky lines per workgroup in the spectrum pass: largest of 4, 2, 1 that fits LDS
+  P.B = 1;
+  for (int B : {4, 2}) {
+    const size_t lds = sizeof(cplx<T>) * size_t(op->Lx) * (1 + B * st.nz);
+    if (op->Ly % B == 0 && lds <= op->lds_max) {
+      P.B = B;
+      break;
+    }
+  }
+}
+
+template <typename T>
+static ConvArgs conv_args(aim_op* op, const PrecData<T>& P, int R) {
+  ConvArgs a{};
+  a.R = R;
+  a.nx = op->st.nx;
+  a.ny = op->st.ny;
+  a.nz = op->st.nz;
+  a.B = P.B;
+  a.Px = op->Px;
+  a.Py = op->Py;
+  a.tw_x = P.tw_x;
+  a.tw_y = P.tw_y;
+  a.gt = P.gt;
+  a.rev_x = op->rev_x;
+  a.rev_y = op->rev_y;
+  return a;
+}
+
+static ProjArgs proj_args(aim_op* op, int R) {
+  const Setup& st = op->st;
+  ProjArgs a{};
+  a.R = R;
+  a.ne = op->ne;
+  a.N = st.N;
+  a.px = op->arr.px;
+  a.py = op->arr.py;
+  a.pitch = op->arr.pitch;
+  a.ex = st.ex;
+  a.ey = st.ey;
+  a.ez = st.ez;
+  a.nx = st.nx;
+  a.ny = st.ny;
+  a.nz = st.nz;
+  a.q3 = st.q3;
+  a.node_ptr = op->node_ptr;
+  a.node_ent = op->node_ent;
+  return a;
+}
+
+static CombineArgs combine_args(aim_op* op, int R) {
+  const Setup& st = op->st;
+  CombineArgs a{};
+  a.R = R;
+  a.ne = op->ne;
+  a.N = st.N;
+  a.px = op->arr.px;
+  a.pitch = op->arr.pitch;
+  a.nx = st.nx;
+  a.ny = st.ny;
+  a.nz = st.nz;
+  a.q = st.q;
+  a.q3 = st.q3;
+  a.n_off = int(st.offsets.size() / 2);
+  a.keta = op->arr.k * op->arr.eta;
+  a.sig_phi = -1.0 / (op->arr.k * op->arr.k);
+  a.sloc = op->sloc;
+  a.near_ptr = op->near_ptr;
+  a.near_col = op->near_col;
+  a.nbr = op->nbr;
+  a.d_ptr = op->d_ptr;
+  a.d_col = op->d_col;
+  return a;
+}
+
+static GemmArgs gemm_args(aim_op* op, int R) {
+  GemmArgs a{};
+  a.N = op->N;
+  a.R = R;
+  a.n_types = op->n_types;
+  a.col_list = op->col_list;
+  a.tile_start[0] = 0;
+  for (int t = 0; t < op->n_types; ++t) {
+    a.type_count[t] = op->type_count[t];
+    a.col_start[t] = op->col_start[t];
+    a.tile_start[t + 1] = a.tile_start[t] + (R * op->type_count[t] + 63) / 64;
+  }
+  return a;
+}
+
+template <typename T>
+PrecData<T>& prec_data(aim_op* op);
+template <>
+PrecData<double>& prec_data<double>(aim_op* op) {
+  return op->p64;
+}
+template <>
+PrecData<float>& prec_data<float>(aim_op* op) {
+  return op->p32;
+}
+
+static int check_common(aim_op* op, const void* a, const void* b, int32_t nrhs, int32_t precision) {
+  if (!op) {
+    set_error("op is NULL");
+    return AIM_EINVAL;
+  }
+  if (!op->device_ready) {
+    set_error("op was built without device data (aim_build_host)");
+    return AIM_ESTATE;
+  }
+  if (!a || !b) {
+    set_error("device pointers must not be NULL");
+    return AIM_EINVAL;
+  }
+  if (nrhs < 1 || nrhs > op->R_max) {
+    set_error("nrhs must be in [1, max_rhs]");
+    return AIM_EINVAL;
+  }
+  if (precision != AIM_FP64 && precision != AIM_MIXED) {
+    set_error("precision must be AIM_FP64 or AIM_MIXED");
+    return AIM_EINVAL;
+  }
+  return AIM_OK;
+}
+
+// ev (optional): 7 events recorded before the first kernel and after each of the six.
+template <typename T>
+int matvec_impl(aim_op* op, const cplx<T>* x, cplx<T>* y, int R, int flags, hipStream_t s, hipEvent_t* ev = nullptr) {
+  PrecData<T>& P = prec_data<T>(op);
+  cplx<T>* u = static_cast<cplx<T>*>(op->u);
+  cplx<T>* grid = static_cast<cplx<T>*>(op->grid);
+  cplx<T>* S = static_cast<cplx<T>*>(op->S);
+  const cplx<T>* src = x;
+  if (ev) AIM_HIP(hipEventRecord(ev[0], s));
+  if (flags == AIM_FULL) {
+    AIM_HIP(launch_macro<T>(P.M, x, u, gemm_args(op, R), s));
+    src = u;
+  }
+  if (ev) AIM_HIP(hipEventRecord(ev[1], s));
+  AIM_HIP(launch_project<T>(src, grid, proj_args(op, R), P.Wp, s));
+  if (ev) AIM_HIP(hipEventRecord(ev[2], s));
+  AIM_HIP(launch_convolve<T>(grid, grid, S, conv_args(op, P, R), s, ev ? ev + 3 : nullptr));
+  if (ev) AIM_HIP(hipEventRecord(ev[5], s));
+  AIM_HIP(launch_combine<T>(flags, grid, src, x, y, combine_args(op, R), P.Wt, P.near, P.dval, s));
+  if (ev) AIM_HIP(hipEventRecord(ev[6], s));
+  return AIM_OK;
+}
+
+template int matvec_impl<double>(aim_op*, const cplx<double>*, cplx<double>*, int, int, hipStream_t, hipEvent_t*);
+template int matvec_impl<float>(aim_op*, const cplx<float>*, cplx<float>*, int, int, hipStream_t, hipEvent_t*);
+
+template <typename T>
+static int time_kernels(aim_op* op, const cplx<T>* x, cplx<T>* y, int R, int reps, double* ms, hipStream_t s) {
+  hipEvent_t ev[7];
+  for (auto& e : ev) AIM_HIP(hipEventCreate(&e));
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  int rc = AIM_OK;
+  for (int it = 0; it <= reps && rc == AIM_OK; ++it) {
+    rc = matvec_impl<T>(op, x, y, R, AIM_FULL, s, ev);
+    if (rc) break;
+    if (hipEventSynchronize(ev[6]) != hipSuccess) {
+      set_error("event synchronisation failed");
+      rc = AIM_EDEVICE;
+      break;
+    }
+    if (it == 0) continue;  // warm-up
+    for (int k = 0; k < 6; ++k) {
+      float t = 0;
+      (void)hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+      acc[k] += t;
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (rc == AIM_OK)
+    for (int k = 0; k < 6; ++k) ms[k] = acc[k] / reps;
+  return rc;
+}
+
+}  // namespace aimm
+
+using namespace aimm;
+
+extern "C" {
+
+const char* aim_last_error(void) { return aimm::g_err.c_str(); }
+
+static int build_op(const aim_surface* surface, const aim_array* array, aim_op** out, bool device) {
+  if (!surface || !array || !out) {
+    set_error("surface, array and out must not be NULL");
+    return AIM_EINVAL;
+  }
+  SurfaceIn s;
+  s.n_vert = surface->n_vert;
+  s.n_tri = surface->n_tri;
+  s.n_rwg = surface->n_rwg;
+  s.vert = surface->vert;
+  s.tri = surface->tri;
+  s.rwg = surface->rwg;
+  ArrayIn a;
+  a.k = array->k;
+  a.eta = array->eta;
+  a.h = array->h;
+  a.r_near = array->r_near;
+  a.order = array->order;
+  a.px = array->px;
+  a.py = array->py;
+  a.pitch = array->pitch_cells;
+  a.n_types = array->n_types;
+  a.elem_type = array->elem_type;
+  a.max_rhs = array->max_rhs;
+  aim_op* op = nullptr;
+  try {
+    validate(s, a);
+    if (a.n_types > kMaxTypes) throw std::invalid_argument("n_types exceeds 16");
+    op = new aim_op();
+    op->vert.assign(s.vert, s.vert + 3 * s.n_vert);
+    op->tri.assign(s.tri, s.tri + 3 * s.n_tri);
+    op->rwg.assign(s.rwg, s.rwg + 4 * s.n_rwg);
+    op->elem_type.assign(a.elem_type, a.elem_type + a.px * a.py);
+    s.vert = op->vert.data();
+    s.tri = op->tri.data();
+    s.rwg = op->rwg.data();
+    a.elem_type = op->elem_type.data();
+    op->arr = a;
+    build_setup(s, a, op->st);
+    Setup& st = op->st;
+    if (st.nz > kMaxNz) throw std::invalid_argument("grid extent along z exceeds 16 nodes");
+    op->ne = a.px * a.py;
+    op->N = st.N;
+    op->R_max = a.max_rhs;
+    op->n_types = a.n_types;
+    op->Lx = smooth_length(std::max(2 * st.nx - 2, st.nx));
+    op->Ly = smooth_length(std::max(2 * st.ny - 2, st.ny));
+    std::vector<int> rx, px_, ry, py_;
+    op->Px = make_plan(op->Lx, rx, px_);
+    op->Py = make_plan(op->Ly, ry, py_);
+    if (!device) {
+      *out = op;
+      return AIM_OK;
+    }
+    op->device_ready = true;
+    if (hipGetDevice(&op->device) != hipSuccess) throw std::runtime_error("no HIP device");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, op->device) != hipSuccess) throw std::runtime_error("device query failed");
+    op->lds_max = prop.sharedMemPerBlock;
+    // integer tables
+    op->sloc = upload(op, st.sloc.data(), st.sloc.size());
+    op->node_ptr = upload(op, st.node_ptr.data(), st.node_ptr.size());
+    op->node_ent = upload(op, st.node_ent.data(), st.node_ent.size());
+    op->near_ptr = upload(op, st.near_ptr.data(), st.near_ptr.size());
+    op->near_col = upload(op, st.near_col.data(), st.near_col.size());
+    op->rev_x = upload(op, rx.data(), rx.size());
+    op->rev_y = upload(op, ry.data(), ry.size());
+    const int n_off = int(st.offsets.size() / 2);
+    std::vector<int> nbr(size_t(op->ne) * std::max(n_off, 1), -1);
+    for (int m = 0; m < op->ne; ++m) {
+      const int ix = m % a.px, iy = m / a.px;
+      for (int o = 0; o < n_off; ++o) {
+        const int jx = ix + st.offsets[2 * o], jy = iy + st.offsets[2 * o + 1];
+        if (jx >= 0 && jx < a.px && jy >= 0 && jy < a.py) nbr[size_t(m) * n_off + o] = jy * a.px + jx;
+      }
+    }
+    op->nbr = upload(op, nbr.data(), nbr.size());
+    // macromodel column lists, r-major within each kind
+    op->type_count.assign(a.n_types, 0);
+    op->col_start.assign(a.n_types, 0);
+    std::vector<int> cols;
+    for (int t = 0; t < a.n_types; ++t) {
+      op->col_start[t] = int(cols.size());
+      std::vector<int> el;
+      for (int m = 0; m < op->ne; ++m)
+        if (a.elem_type[m] == t) el.push_back(m);
+      op->type_count[t] = int(el.size());
+      for (int r = 0; r < a.max_rhs; ++r)
+        for (int m : el) cols.push_back(r * op->ne + m);
+    }
+    op->col_list = upload(op, cols.data(), cols.size());
+    fill_prec(op, op->p64);
+    fill_prec(op, op->p32);
+    // FFT workgroups may need more than the default dynamic LDS
+    const size_t lmax = std::min<size_t>(op->lds_max, 160 * 1024);
+    (void)configure_lds(lmax);
+    // kernel spectrum on the device (FP64), then stored in both precisions
+    {
+      const size_t lds_y = sizeof(cplx<double>) * size_t(op->Ly) * (1 + st.nz);
+      const size_t lds_x = sizeof(cplx<double>) * size_t(op->Lx) * (1 + st.nz);
+      if (lds_y > op->lds_max || lds_x > op->lds_max)
+        throw std::invalid_argument("padded grid too large for one workgroup's LDS in FP64");
+      cplx<double>* raw = op->mem.alloc<cplx<double>>(size_t(op->Lx) * op->Ly * st.nz);
+      int* pxd = upload(op, px_.data(), px_.size());
+      int* pyd = upload(op, py_.data(), py_.size());
+      hipError_t e = launch_spectrum(raw, op->Lx, op->Ly, st.nz, a.k, a.h, op->Px, op->Py, op->p64.tw_x,
+                                     op->p64.tw_y, 1, nullptr);
+      if (e == hipSuccess) e = launch_extract<double>(raw, op->p64.gt, op->Lx, op->Ly, st.nz, pxd, pyd, nullptr);
+      if (e == hipSuccess) e = launch_extract<float>(raw, op->p32.gt, op->Lx, op->Ly, st.nz, pxd, pyd, nullptr);
+      if (e == hipSuccess) e = hipDeviceSynchronize();
+      if (e != hipSuccess) throw std::runtime_error(std::string("spectrum build: ") + hipGetErrorString(e));
+      op->mem.release(raw, sizeof(cplx<double>) * size_t(op->Lx) * op->Ly * st.nz);
+      op->mem.release(pxd, sizeof(int) * px_.size());
+      op->mem.release(pyd, sizeof(int) * py_.size());
+    }
+    // workspaces, sized for complex128
+    const size_t n_unk = size_t(op->ne) * op->N * a.max_rhs;
+    op->u = op->mem.alloc<cplx<double>>(n_unk);
+    op->grid = op->mem.alloc<cplx<double>>(size_t(a.max_rhs) * 4 * st.nx * st.ny * st.nz);
+    op->S = op->mem.alloc<cplx<double>>(size_t(a.max_rhs) * 4 * st.nx * op->Ly * st.nz);
+  } catch (const std::bad_alloc&) {
+    delete op;
+    set_error("device or host allocation failed");
+    return AIM_ENOMEM;
+  } catch (const std::invalid_argument& e) {
+    delete op;
+    set_error(e.what());
+    return AIM_EINVAL;
+  } catch (const std::exception& e) {
+    delete op;
+    set_error(e.what());
+    return AIM_EDEVICE;
+  }
+  *out = op;
+  return AIM_OK;
+}
+
+int aim_build_grid(const aim_surface* surface, const aim_array* array, aim_op** out) {
+  return build_op(surface, array, out, true);
+}
+
+int aim_build_host(const aim_surface* surface, const aim_array* array, aim_op** out) {
+  return build_op(surface, array, out, false);
+}
+
+int aim_set_macromodels(aim_op* op, const double* M) {
+  if (!op || !M) {
+    set_error("op and M must not be NULL");
+    return AIM_EINVAL;
+  }
+  if (!op->device_ready) {
+    set_error("op was built without device data (aim_build_host)");
+    return AIM_ESTATE;
+  }
+  const size_t n = size_t(op->n_types) * op->N * op->N;
+  try {
+    if (!op->p64.M) {
+      op->p64.M = op->mem.alloc<cplx<double>>(n);
+      op->p32.M = op->mem.alloc<cplx<float>>(n);
+    }
+    std::vector<cplx<float>> m32(n);
+    for (size_t i = 0; i < n; ++i) {
+      m32[i].re = float(M[2 * i]);
+      m32[i].im = float(M[2 * i + 1]);
+    }
+    AIM_HIP(hipMemcpy(op->p64.M, M, n * sizeof(cplx<double>), hipMemcpyHostToDevice));
+    AIM_HIP(hipMemcpy(op->p32.M, m32.data(), n * sizeof(cplx<float>), hipMemcpyHostToDevice));
+  } catch (const std::bad_alloc&) {
+    set_error("device allocation failed");
+    return AIM_ENOMEM;
+  }
+  op->m_set = true;
+  return AIM_OK;
+}
+
+int aim_set_dmatrix(aim_op* op, int64_t nnz, const int32_t* rows, const int32_t* cols, const double* vals) {
+  if (!op || nnz < 0 || (nnz > 0 && (!rows || !cols || !vals))) {
+    set_error("bad D arguments");
+    return AIM_EINVAL;
+  }
+  const int N = op->N;
+  for (int64_t i = 0; i < nnz; ++i)
+    if (rows[i] < 0 || rows[i] >= N || cols[i] < 0 || cols[i] >= N) {
+      set_error("D index out of range");
+      return AIM_EINVAL;
+    }
+  if (op->d_set) {
+    set_error("D is already set");
+    return AIM_ESTATE;
+  }
+  if (!op->device_ready) {
+    set_error("op was built without device data (aim_build_host)");
+    return AIM_ESTATE;
+  }
+  // CSR by row, columns in input order within a row
+  std::vector<int> ptr(N + 1, 0), col(nnz);
+  std::vector<cplx<double>> v64(nnz);
+  std::vector<cplx<float>> v32(nnz);
+  for (int64_t i = 0; i < nnz; ++i) ptr[rows[i] + 1]++;
+  for (int n = 0; n < N; ++n) ptr[n + 1] += ptr[n];
+  std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+  for (int64_t i = 0; i < nnz; ++i) {
+    const int at = fill[rows[i]]++;
+    col[at] = cols[i];
+    v64[at].re = vals[2 * i];
+    v64[at].im = vals[2 * i + 1];
+    v32[at].re = float(vals[2 * i]);
+    v32[at].im = float(vals[2 * i + 1]);
+  }
+  try {
+    op->d_ptr = upload(op, ptr.data(), ptr.size());
+    op->d_col = upload(op, col.data(), col.size());
+    op->p64.dval = upload(op, v64.data(), v64.size());
+    op->p32.dval = upload(op, v32.data(), v32.size());
+  } catch (const std::bad_alloc&) {
+    set_error("device allocation failed");
+    return AIM_ENOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return AIM_EDEVICE;
+  }
+  op->d_nnz = nnz;
+  op->d_set = true;
+  return AIM_OK;
+}
+
+int macro_apply(aim_op* op, const void* x, void* u, int32_t nrhs, int32_t precision, void* stream) {
+  int c = check_common(op, x, u, nrhs, precision);
+  if (c) return c;
+  if (!op->m_set) {
+    set_error("macromodels not set");
+    return AIM_ESTATE;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (precision == AIM_FP64)
+    AIM_HIP(launch_macro<double>(op->p64.M, static_cast<const cplx<double>*>(x), static_cast<cplx<double>*>(u),
+                                 gemm_args(op, nrhs), s));
+  else
+    AIM_HIP(launch_macro<float>(op->p32.M, static_cast<const cplx<float>*>(x), static_cast<cplx<float>*>(u),
+                                gemm_args(op, nrhs), s));
+  return AIM_OK;
+}
+
+int aim_matvec(aim_op* op, const void* x, void* y, int32_t nrhs, int32_t precision, int32_t flags, void* stream) {
+  int c = check_common(op, x, y, nrhs, precision);
+  if (c) return c;
+  if (flags < AIM_FULL || flags > AIM_FAR_ONLY) {
+    set_error("unknown flags");
+    return AIM_EINVAL;
+  }
+  if (x == y) {
+    set_error("x and y must not alias");
+    return AIM_EINVAL;
+  }
+  if (flags == AIM_FULL && (!op->m_set || !op->d_set)) {
+    set_error("macromodels and D must be set for the full product");
+    return AIM_ESTATE;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (precision == AIM_FP64)
+    return matvec_impl<double>(op, static_cast<const cplx<double>*>(x), static_cast<cplx<double>*>(y), nrhs, flags, s);
+  return matvec_impl<float>(op, static_cast<const cplx<float>*>(x), static_cast<cplx<float>*>(y), nrhs, flags, s);
+}
+
+int aim_time_kernels(aim_op* op, const void* x, void* y, int32_t nrhs, int32_t precision, int32_t reps, double* ms,
+                     void* stream) {
+  int c = check_common(op, x, y, nrhs, precision);
+  if (c) return c;
+  if (!ms || reps < 1 || x == y) {
+    set_error("ms must not be NULL, reps >= 1, x and y must not alias");
+    return AIM_EINVAL;
+  }
+  if (!op->m_set || !op->d_set) {
+    set_error("macromodels and D must be set");
+    return AIM_ESTATE;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (precision == AIM_FP64)
+    return time_kernels<double>(op, static_cast<const cplx<double>*>(x), static_cast<cplx<double>*>(y), nrhs, reps,
+                                ms, s);
+  return time_kernels<float>(op, static_cast<const cplx<float>*>(x), static_cast<cplx<float>*>(y), nrhs, reps, ms, s);
+}
+
+int aim_project(aim_op* op, const void* u, void* Q, int32_t nrhs, int32_t precision, void* stream) {
+  int c = check_common(op, u, Q, nrhs, precision);
+  if (c) return c;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (precision == AIM_FP64)
+    AIM_HIP(launch_project<double>(static_cast<const cplx<double>*>(u), static_cast<cplx<double>*>(Q),
+                                   proj_args(op, nrhs), op->p64.Wp, s));
+  else
+    AIM_HIP(launch_project<float>(static_cast<const cplx<float>*>(u), static_cast<cplx<float>*>(Q),
+                                  proj_args(op, nrhs), op->p32.Wp, s));
+  return AIM_OK;
+}
+
+int aim_convolve(aim_op* op, const void* Q, void* Phi, int32_t nrhs, int32_t precision, void* stream) {
+  int c = check_common(op, Q, Phi, nrhs, precision);
+  if (c) return c;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (precision == AIM_FP64)
+    AIM_HIP(launch_convolve<double>(static_cast<const cplx<double>*>(Q), static_cast<cplx<double>*>(Phi),
+                                    static_cast<cplx<double>*>(op->S), conv_args(op, op->p64, nrhs), s));
+  else
+    AIM_HIP(launch_convolve<float>(static_cast<const cplx<float>*>(Q), static_cast<cplx<float>*>(Phi),
+                                   static_cast<cplx<float>*>(op->S), conv_args(op, op->p32, nrhs), s));
+  return AIM_OK;
+}
+
+int aim_plane_wave_rhs(aim_op* op, const double* theta, const double* phi, const int32_t* pol, int32_t nrhs,
+                       void* b, void* stream) {
+  if (!op || !theta || !phi || !pol || !b || nrhs < 1 || nrhs > op->R_max) {
+    set_error("bad plane-wave arguments");
+    return AIM_EINVAL;
+  }
+  if (!op->device_ready) {
+    set_error("op was built without device data (aim_build_host)");
+    return AIM_ESTATE;
+  }
+  for (int r = 0; r < nrhs; ++r)
+    if (pol[r] != 0 && pol[r] != 1) {
+      set_error("pol must be 0 or 1");
+      return AIM_EINVAL;
+    }
+  SurfaceIn s;
+  s.n_vert = int(op->vert.size() / 3);
+  s.n_tri = int(op->tri.size() / 3);
+  s.n_rwg = int(op->rwg.size() / 4);
+  s.vert = op->vert.data();
+  s.tri = op->tri.data();
+  s.rwg = op->rwg.data();
+  std::vector<cplx<double>> loc(size_t(nrhs) * op->N);
+  std::vector<double> kinc(3 * nrhs);
+  std::vector<cd> l;
+  for (int r = 0; r < nrhs; ++r) {
+    plane_wave_local(s, op->arr.k, theta[r], phi[r], pol[r], l, &kinc[3 * r]);
+    for (int n = 0; n < op->N; ++n) {
+      loc[size_t(r) * op->N + n].re = l[n].real();
+      loc[size_t(r) * op->N + n].im = l[n].imag();
+    }
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  void *dl = nullptr, *dk = nullptr;
+  AIM_HIP(hipMalloc(&dl, loc.size() * sizeof(cplx<double>)));
+  if (hipMalloc(&dk, kinc.size() * sizeof(double)) != hipSuccess) {
+    (void)hipFree(dl);
+    set_error("hipMalloc failed");
+    return AIM_ENOMEM;
+  }
+  hipError_t e = hipMemcpyAsync(dl, loc.data(), loc.size() * sizeof(cplx<double>), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(dk, kinc.data(), kinc.size() * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = launch_expand_rhs(static_cast<cplx<double>*>(dl), static_cast<double*>(dk), static_cast<cplx<double>*>(b),
+                          nrhs, op->ne, op->N, op->arr.px, op->arr.pitch * op->arr.h, op->arr.k, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(dl);
+  (void)hipFree(dk);
+  if (e != hipSuccess) {
+    set_error(std::string("plane-wave rhs: ") + hipGetErrorString(e));
+    return AIM_EDEVICE;
+  }
+  return AIM_OK;
+}
+
+int aim_get_info(const aim_op* op, aim_info* info) {
+  if (!op || !info) {
+    set_error("op and info must not be NULL");
+    return AIM_EINVAL;
+  }
+  info->n_rwg = op->N;
+  info->n_elem = op->ne;
+  info->n_types = op->n_types;
+  info->nx = op->st.nx;
+  info->ny = op->st.ny;
+  info->nz = op->st.nz;
+  info->lx = op->Lx;
+  info->ly = op->Ly;
+  info->n_offsets = int(op->st.offsets.size() / 2);
+  info->near_nnz = int64_t(op->st.near_val.size());
+  info->d_nnz = op->d_nnz;
+  info->device_bytes = int64_t(op->mem.bytes);
+  return AIM_OK;
+}
+
+int aim_get_near(const aim_op* op, int32_t* rows, int32_t* offs, int32_t* cols, double* vals, int32_t* offsets) {
+  if (!op || !rows || !offs || !cols || !vals || !offsets) {
+    set_error("NULL argument");
+    return AIM_EINVAL;
+  }
+  const Setup& st = op->st;
+  for (int n = 0; n < st.N; ++n)
+    for (int e = st.near_ptr[n]; e < st.near_ptr[n + 1]; ++e) {
+      rows[e] = n;
+      offs[e] = st.near_col[e] / st.N;
+      cols[e] = st.near_col[e] % st.N;
+      vals[2 * e] = st.near_val[e].real();
+      vals[2 * e + 1] = st.near_val[e].imag();
+    }
+  for (size_t i = 0; i < st.offsets.size(); ++i) offsets[i] = st.offsets[i];
+  return AIM_OK;
+}
+
+size_t aim_footprint_bytes(const aim_surface* surface, const aim_array* array, int32_t nrhs, int32_t restart,
+                           int32_t precision) {
+  if (!surface || !array || nrhs < 1 || restart < 1) return 0;
+  // stencil extent from the edge midpoints, as in the build
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int n = 0; n < surface->n_rwg; ++n)
+    for (int ax = 0; ax < 3; ++ax) {
+      const double c = 0.5 * (surface->vert[3 * surface->rwg[4 * n] + ax] + surface->vert[3 * surface->rwg[4 * n + 1] + ax]);
+      const double v = std::floor(c / array->h - 0.5 * array->order + 0.5 + 1e-9);
+      lo[ax] = std::min(lo[ax], v);
+      hi[ax] = std::max(hi[ax], v);
+    }
+  const int q = array->order + 1;
+  const size_t ex = size_t(hi[0] - lo[0]) + q, ey = size_t(hi[1] - lo[1]) + q, ez = size_t(hi[2] - lo[2]) + q;
+  const size_t nx = size_t(array->pitch_cells) * (array->px - 1) + ex;
+  const size_t ny = size_t(array->pitch_cells) * (array->py - 1) + ey;
+  const size_t Ly = size_t(smooth_length(int(std::max(2 * ny - 2, ny))));
+  const size_t Lx = size_t(smooth_length(int(std::max(2 * nx - 2, nx))));
+  const size_t N = size_t(surface->n_rwg), ne = size_t(array->px) * array->py, R = size_t(array->max_rhs);
+  const size_t n = ne * N;
+  size_t b = 0;
+  b += n * R * 16;                                   // u
+  b += R * 4 * nx * ny * ez * 16;                    // grid
+  b += R * 4 * nx * Ly * ez * 16;                    // spectrum pass
+  b += (Lx / 2 + 1) * (Ly / 2 + 1) * ez * 24;        // kernel spectrum, both precisions
+  b += size_t(array->n_types) * N * N * 24;          // macromodels
+  b += N * 600 * 28 + N * q * q * q * 4 * 24;        // near field (upper estimate) and weights
+  const size_t vec = precision == AIM_FP64 ? 16 : 8;
+  b += size_t(restart + 1) * size_t(nrhs) * n * vec;  // Krylov basis
+  b += size_t(nrhs) * n * (16 * 3 + 2 * vec);         // GMRES vectors
+  return b;
+}
+
+void aim_destroy(aim_op* op) {
+  if (!op) return;
+  if (op->device_ready) {
+    (void)hipDeviceSynchronize();
+    aimm::release_krylov(op);
+  }
+  delete op;
+}
+
+}  // extern "C"

@@ -1,0 +1,482 @@
+// Restarted GMRES on the final system (section V, eq. finalsystem), one Krylov
+// space per right-hand side, all right-hand sides advanced together.
+//
+// Per cycle: FP64 true residual r = b - A x (FP64 product), v_0 = r / ||r||; then
+// for j = 0 .. m-1: w = A v_j, classical Gram-Schmidt applied twice (CGS2) with
+// FP64 sums, v_{j+1} = w / ||w||, Givens rotations on the FP64 Hessenberg column;
+// finally x += V y with y from the triangular least-squares system.  AIM_MIXED runs
+// the products in complex FP32 and stores the basis in complex FP32; all dot
+// products, norms, the Hessenberg matrix, rotations and x stay FP64.
+// Reductions are split into fixed chunks summed in a fixed order, and no value
+// mixes right-hand sides, so each solution is independent of the batch it ran in.
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "../../include/aimm.h"
+#include "op.hpp"
+
+namespace aimm {
+
+template <typename T>
+int matvec_impl(aim_op* op, const cplx<T>* x, cplx<T>* y, int R, int flags, hipStream_t s, hipEvent_t* ev = nullptr);
+
+namespace {
+
+constexpr int kBS = 256;
+constexpr int kE = 8;
+constexpr int kChunk = kBS * kE;
+
+template <typename T>
+__device__ __forceinline__ cplx<double> up(cplx<T> v) {
+  return cmk<double>(double(v.re), double(v.im));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// block sum of (a, b) pairs; result valid in thread 0
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) {
+    sh[2 * w] = a;
+    sh[2 * w + 1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = 0;
+    b = 0;
+    for (int i = 0; i < kBS / 64; ++i) {
+      a += sh[2 * i];
+      b += sh[2 * i + 1];
+    }
+  }
+}
+
+// part[(r * nv + i) * nch + c] = sum over chunk c of conj(V_i[r]) . w[r], i < nv
+template <typename Tb>
+__global__ void __launch_bounds__(kBS) k_dots(const cplx<Tb>* __restrict__ V, const cplx<double>* __restrict__ w,
+                                              double* __restrict__ part, int64_t n, int nv, int R) {
+  __shared__ double sh[2 * kBS / 64];
+  const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
+  const int64_t base = int64_t(c) * kChunk;
+  cplx<double> wl[kE];
+#pragma unroll
+  for (int e = 0; e < kE; ++e) {
+    const int64_t k = base + e * kBS + threadIdx.x;
+    wl[e] = k < n ? w[int64_t(r) * n + k] : cmk<double>(0, 0);
+  }
+  for (int i = 0; i < nv; ++i) {
+    const cplx<Tb>* vi = V + (int64_t(i) * R + r) * n;
+    double a = 0, b = 0;
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+      const int64_t k = base + e * kBS + threadIdx.x;
+      if (k < n) {
+        const cplx<double> v = up(vi[k]);
+        a += v.re * wl[e].re + v.im * wl[e].im;
+        b += v.re * wl[e].im - v.im * wl[e].re;
+      }
+    }
+    block_sum2(a, b, sh);
+    if (threadIdx.x == 0) {
+      part[(int64_t(r) * nv + i) * nch * 2 + 2 * c] = a;
+      part[(int64_t(r) * nv + i) * nch * 2 + 2 * c + 1] = b;
+    }
+  }
+}
+
+// h[r][i] (+)= sum_c part ; one thread per (r, i)
+__global__ void k_reduce_dots(const double* __restrict__ part, cplx<double>* h, int nch, int nv, int R, int ldh,
+                              int accumulate) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nv * R) return;
+  const int r = t / nv, i = t - r * nv;
+  const double* p = part + int64_t(t) * nch * 2;
+  double a = 0, b = 0;
+  for (int c = 0; c < nch; ++c) {
+    a += p[2 * c];
+    b += p[2 * c + 1];
+  }
+  cplx<double>& o = h[int64_t(r) * ldh + i];
+  if (accumulate) {
+    o.re += a;
+    o.im += b;
+  } else {
+    o.re = a;
+    o.im = b;
+  }
+}
+
+// w[r] -= sum_{i<nv} V_i[r] * coef[r][i]; optionally chunk partials of ||w||^2
+template <typename Tb>
+__global__ void __launch_bounds__(kBS) k_update(const cplx<Tb>* __restrict__ V, cplx<double>* __restrict__ w,
+                                                const cplx<double>* __restrict__ coef, int ldc, double* part,
+                                                int64_t n, int nv, int R, int with_norm) {
+  __shared__ double sh[2 * kBS / 64];
+  const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
+  const int64_t base = int64_t(c) * kChunk;
+  const cplx<double>* cf = coef + int64_t(r) * ldc;
+  double nn = 0, dummy = 0;
+#pragma unroll
+  for (int e = 0; e < kE; ++e) {
+    const int64_t k = base + e * kBS + threadIdx.x;
+    if (k >= n) continue;
+    cplx<double> acc = w[int64_t(r) * n + k];
+    for (int i = 0; i < nv; ++i) {
+      const cplx<double> v = up(V[(int64_t(i) * R + r) * n + k]);
+      const cplx<double> h = cf[i];
+      acc.re -= v.re * h.re - v.im * h.im;
+      acc.im -= v.re * h.im + v.im * h.re;
+    }
+    w[int64_t(r) * n + k] = acc;
+    nn += acc.re * acc.re + acc.im * acc.im;
+  }
+  if (with_norm) {
+    block_sum2(nn, dummy, sh);
+    if (threadIdx.x == 0) part[int64_t(r) * nch + c] = nn;
+  }
+}
+
+// chunk partials of ||a - b||^2 (b may be null) and of the difference into out
+__global__ void __launch_bounds__(kBS) k_residual(const cplx<double>* __restrict__ a, const cplx<double>* __restrict__ b,
+                                                  cplx<double>* __restrict__ out, double* part, int64_t n) {
+  __shared__ double sh[2 * kBS / 64];
+  const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
+  const int64_t base = int64_t(c) * kChunk;
+  double nn = 0, dummy = 0;
+#pragma unroll
+  for (int e = 0; e < kE; ++e) {
+    const int64_t k = base + e * kBS + threadIdx.x;
+    if (k >= n) continue;
+    const int64_t idx = int64_t(r) * n + k;
+    cplx<double> v = a[idx];
+    if (b) v = csub(v, b[idx]);
+    if (out) out[idx] = v;
+    nn += v.re * v.re + v.im * v.im;
+  }
+  block_sum2(nn, dummy, sh);
+  if (threadIdx.x == 0) part[int64_t(r) * nch + c] = nn;
+}
+
+// out[r] = sqrt(sum_c part[r][c])
+__global__ void k_finish_norm(const double* part, double* out, int nch, int R, int stride) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  double s = 0;
+  for (int c = 0; c < nch; ++c) s += part[int64_t(r) * nch + c];
+  out[r * stride] = sqrt(s);
+}
+
+// v[r] = w[r] / nrm[r] (zero if nrm = 0), stored in the basis precision
+template <typename Tb>
+__global__ void k_scale(const cplx<double>* __restrict__ w, cplx<Tb>* __restrict__ v, const double* nrm, int stride,
+                        int64_t n, int R) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n * R) return;
+  const int r = int(t / n);
+  const double d = nrm[r * stride];
+  const double s = d > 0 ? 1.0 / d : 0.0;
+  v[t] = cmk<Tb>(Tb(w[t].re * s), Tb(w[t].im * s));
+}
+
+template <typename Tb>
+__global__ void k_up(const cplx<Tb>* __restrict__ in, cplx<double>* __restrict__ out, int64_t n) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < n) out[t] = up(in[t]);
+}
+
+// Givens step on column j, one thread per right-hand side.
+//   H[r]: (m+1) x m column-major (ld m+1); h1, h2: the two Gram-Schmidt passes
+//   ([r][m+1]); scal[4r] = ||w||, scal[4r+1] = stop threshold on |g|,
+//   scal[4r+2] = iteration budget of this cycle; jused[r] = 0 while running, set to
+//   j+1 when the residual estimate passes the threshold or the budget runs out,
+//   negative for right-hand sides that are already finished.
+__global__ void k_givens(cplx<double>* H, cplx<double>* cs, cplx<double>* sn, cplx<double>* g,
+                         const cplx<double>* h1, const cplx<double>* h2, const double* scal, int* jused, int m,
+                         int j, int R) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R || jused[r] != 0) return;
+  cplx<double>* Hc = H + (int64_t(r) * m + j) * (m + 1);
+  cplx<double>* c = cs + int64_t(r) * m;
+  cplx<double>* s = sn + int64_t(r) * m;
+  cplx<double>* gg = g + int64_t(r) * (m + 1);
+  for (int i = 0; i <= j; ++i) Hc[i] = cadd(h1[int64_t(r) * (m + 1) + i], h2[int64_t(r) * (m + 1) + i]);
+  Hc[j + 1] = cmk<double>(scal[4 * r], 0.0);
+  for (int i = 0; i < j; ++i) {
+    const cplx<double> p = Hc[i], q = Hc[i + 1];
+    Hc[i] = cadd(cmulc(p, c[i]), cmulc(q, s[i]));  // conj(c) p + conj(s) q
+    Hc[i + 1] = csub(cmul(c[i], q), cmul(s[i], p));  // -s p + c q
+  }
+  const cplx<double> a = Hc[j], b = Hc[j + 1];
+  const double den = sqrt(a.re * a.re + a.im * a.im + b.re * b.re + b.im * b.im);
+  if (den > 0) {
+    c[j] = cmk<double>(a.re / den, a.im / den);
+    s[j] = cmk<double>(b.re / den, b.im / den);
+  } else {
+    c[j] = cmk<double>(1.0, 0.0);
+    s[j] = cmk<double>(0.0, 0.0);
+  }
+  Hc[j] = cmk<double>(den, 0.0);
+  Hc[j + 1] = cmk<double>(0.0, 0.0);
+  const cplx<double> gj = gg[j];
+  gg[j + 1] = cmk<double>(-(s[j].re * gj.re - s[j].im * gj.im), -(s[j].re * gj.im + s[j].im * gj.re));
+  gg[j] = cmulc(gj, c[j]);  // conj(c) g_j
+  const double est = sqrt(gg[j + 1].re * gg[j + 1].re + gg[j + 1].im * gg[j + 1].im);
+  if (est <= scal[4 * r + 1] || double(j + 1) >= scal[4 * r + 2]) jused[r] = j + 1;
+}
+
+// y = H^-1 g on the leading k columns (back substitution); k = jused[r] if set,
+// j_end if still running, 0 for finished right-hand sides.
+__global__ void k_lsq(const cplx<double>* H, const cplx<double>* g, cplx<double>* y, const int* jused, int m, int R,
+                      int j_end) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const int k = jused[r] > 0 ? jused[r] : (jused[r] == 0 ? j_end : 0);
+  const cplx<double>* Hr = H + int64_t(r) * m * (m + 1);
+  cplx<double>* yr = y + int64_t(r) * (m + 1);
+  for (int i = k; i <= m; ++i) yr[i] = cmk<double>(0, 0);
+  for (int i = k - 1; i >= 0; --i) {
+    cplx<double> acc = g[int64_t(r) * (m + 1) + i];
+    for (int l = i + 1; l < k; ++l) acc = csub(acc, cmul(Hr[int64_t(l) * (m + 1) + i], yr[l]));
+    const cplx<double> d = Hr[int64_t(i) * (m + 1) + i];
+    const double dd = d.re * d.re + d.im * d.im;
+    yr[i] = dd > 0 ? cmk<double>((acc.re * d.re + acc.im * d.im) / dd, (acc.im * d.re - acc.re * d.im) / dd)
+                   : cmk<double>(0, 0);
+  }
+}
+
+// x[r] += sum_i V_i[r] y[r][i]  (y is zero beyond the used columns)
+template <typename Tb>
+__global__ void k_update_x(const cplx<Tb>* __restrict__ V, cplx<double>* __restrict__ x,
+                           const cplx<double>* __restrict__ y, int64_t n, int nv, int R, int m) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n * R) return;
+  const int r = int(t / n);
+  const int64_t k = t - int64_t(r) * n;
+  cplx<double> acc = x[t];
+  const cplx<double>* yr = y + int64_t(r) * (m + 1);
+  for (int i = 0; i < nv; ++i) cfma(acc, up(V[(int64_t(i) * R + r) * n + k]), yr[i]);
+  x[t] = acc;
+}
+
+inline unsigned nblk(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
+
+#define GM_HIP(expr)                                                              \
+  do {                                                                            \
+    hipError_t _e = (expr);                                                       \
+    if (_e != hipSuccess) {                                                       \
+      set_error(std::string("gmres: ") + #expr + ": " + hipGetErrorString(_e));  \
+      return AIM_EDEVICE;                                                         \
+    }                                                                             \
+  } while (0)
+
+#define GM_LAUNCH(...)                      \
+  do {                                      \
+    hipLaunchKernelGGL(__VA_ARGS__);        \
+    GM_HIP(hipGetLastError());              \
+  } while (0)
+
+template <typename Tb>
+int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const gmres_opts& o, gmres_stat* st,
+               hipStream_t s) {
+  KrylovWork& K = op->kw;
+  const int64_t n = int64_t(op->ne) * op->N;
+  const int m = o.restart;
+  const int nch = int((n + kChunk - 1) / kChunk);
+  const dim3 gch(nch, R), bs(kBS), g64(nblk(R, 64)), b64(64);
+  cplx<Tb>* V = static_cast<cplx<Tb>*>(K.V);
+  GM_LAUNCH(k_residual, gch, bs, 0, s, b, (const cplx<double>*)nullptr, (cplx<double>*)nullptr, K.part, n);
+  GM_LAUNCH(k_finish_norm, g64, b64, 0, s, K.part, K.scal + 3, nch, R, 4);
+  if (!o.x0_given) GM_HIP(hipMemsetAsync(x, 0, sizeof(cplx<double>) * n * R, s));
+  std::vector<double> bnorm(R), relres(R, 1.0), hs(4 * R);
+  std::vector<int> active(R, 1), iters(R, 0), restarts(R, 0), matvecs(R, 0), jused(R), jinit(R);
+  GM_HIP(hipMemcpyAsync(hs.data(), K.scal, sizeof(double) * 4 * R, hipMemcpyDeviceToHost, s));
+  GM_HIP(hipStreamSynchronize(s));
+  for (int r = 0; r < R; ++r) bnorm[r] = hs[4 * r + 3];
+  std::vector<cplx<double>> g0(size_t(R) * (m + 1));
+  const int check = std::max(1, o.check_every);
+  for (;;) {
+    // FP64 true residual r = b - A x
+    int rc = matvec_impl<double>(op, x, K.w, R, AIM_FULL, s);
+    if (rc) return rc;
+    GM_LAUNCH(k_residual, gch, bs, 0, s, b, K.w, K.r, K.part, n);
+    GM_LAUNCH(k_finish_norm, g64, b64, 0, s, K.part, K.scal, nch, R, 4);
+    GM_HIP(hipMemcpyAsync(hs.data(), K.scal, sizeof(double) * 4 * R, hipMemcpyDeviceToHost, s));
+    GM_HIP(hipStreamSynchronize(s));
+    bool any = false;
+    int budget_max = 0;
+    for (int r = 0; r < R; ++r) {
+      if (!active[r]) continue;
+      matvecs[r] += 1;
+      relres[r] = bnorm[r] > 0 ? hs[4 * r] / bnorm[r] : 0.0;
+      if (relres[r] <= o.tol || iters[r] >= o.max_iters) {
+        active[r] = 0;
+        continue;
+      }
+      any = true;
+      budget_max = std::max(budget_max, std::min(m, o.max_iters - iters[r]));
+    }
+    if (!any) break;
+    for (int r = 0; r < R; ++r) {
+      hs[4 * r + 1] = o.tol * bnorm[r];
+      hs[4 * r + 2] = active[r] ? double(std::min(m, o.max_iters - iters[r])) : 0.0;
+      jinit[r] = active[r] ? 0 : -1;
+      g0[size_t(r) * (m + 1)] = cplx<double>{active[r] ? hs[4 * r] : 0.0, 0.0};
+    }
+    GM_HIP(hipMemcpyAsync(K.scal, hs.data(), sizeof(double) * 4 * R, hipMemcpyHostToDevice, s));
+    GM_HIP(hipMemcpyAsync(K.active, jinit.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
+    GM_HIP(hipMemcpyAsync(K.g, g0.data(), sizeof(cplx<double>) * g0.size(), hipMemcpyHostToDevice, s));
+    GM_LAUNCH(k_scale<Tb>, dim3(nblk(n * R, 256)), dim3(256), 0, s, K.r, V, K.scal, 4, n, R);
+    int j_end = 0;
+    for (int j = 0; j < budget_max; ++j) {
+      const cplx<Tb>* vj = V + int64_t(j) * R * n;
+      if (sizeof(Tb) == sizeof(double)) {
+        rc = matvec_impl<double>(op, reinterpret_cast<const cplx<double>*>(vj), K.w, R, AIM_FULL, s);
+        if (rc) return rc;
+      } else {
+        rc = matvec_impl<float>(op, reinterpret_cast<const cplx<float>*>(vj), static_cast<cplx<float>*>(K.ylow), R,
+                                AIM_FULL, s);
+        if (rc) return rc;
+        GM_LAUNCH(k_up<float>, dim3(nblk(n * R, 256)), dim3(256), 0, s, static_cast<const cplx<float>*>(K.ylow),
+                  K.w, n * R);
+      }
+      const int nv = j + 1;
+      // classical Gram-Schmidt, twice
+      GM_LAUNCH(k_dots<Tb>, gch, bs, 0, s, V, K.w, K.part, n, nv, R);
+      GM_LAUNCH(k_reduce_dots, dim3(nblk(nv * R, 64)), b64, 0, s, K.part, K.hcol, nch, nv, R, m + 1, 0);
+      GM_LAUNCH(k_update<Tb>, gch, bs, 0, s, V, K.w, K.hcol, m + 1, K.part, n, nv, R, 0);
+      GM_LAUNCH(k_dots<Tb>, gch, bs, 0, s, V, K.w, K.part, n, nv, R);
+      GM_LAUNCH(k_reduce_dots, dim3(nblk(nv * R, 64)), b64, 0, s, K.part, K.h2, nch, nv, R, m + 1, 0);
+      GM_LAUNCH(k_update<Tb>, gch, bs, 0, s, V, K.w, K.h2, m + 1, K.part, n, nv, R, 1);
+      GM_LAUNCH(k_finish_norm, g64, b64, 0, s, K.part, K.scal, nch, R, 4);
+      GM_LAUNCH(k_scale<Tb>, dim3(nblk(n * R, 256)), dim3(256), 0, s, K.w, V + int64_t(j + 1) * R * n, K.scal, 4, n,
+                R);
+      GM_LAUNCH(k_givens, g64, b64, 0, s, K.H, K.cs, K.sn, K.g, K.hcol, K.h2, K.scal, K.active, m, j, R);
+      j_end = j + 1;
+      if (j_end % check == 0 || j_end == budget_max) {
+        GM_HIP(hipMemcpyAsync(jused.data(), K.active, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+        GM_HIP(hipStreamSynchronize(s));
+        bool all = true;
+        for (int r = 0; r < R; ++r)
+          if (jused[r] == 0) all = false;
+        if (all) break;
+      }
+    }
+    GM_LAUNCH(k_lsq, g64, b64, 0, s, K.H, K.g, K.h2, K.active, m, R, j_end);
+    GM_LAUNCH(k_update_x<Tb>, dim3(nblk(n * R, 256)), dim3(256), 0, s, V, x, K.h2, n, j_end, R, m);
+    GM_HIP(hipMemcpyAsync(jused.data(), K.active, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    GM_HIP(hipStreamSynchronize(s));
+    for (int r = 0; r < R; ++r) {
+      if (!active[r]) continue;
+      const int k = jused[r] > 0 ? jused[r] : j_end;
+      iters[r] += k;
+      matvecs[r] += k;
+      restarts[r] += 1;
+    }
+  }
+  bool all_conv = true;
+  for (int r = 0; r < R; ++r) {
+    st[r].iters = iters[r];
+    st[r].restarts = restarts[r];
+    st[r].matvecs = matvecs[r];
+    st[r].true_relres = relres[r];
+    st[r].converged = relres[r] <= o.tol ? 1 : 0;
+    if (!st[r].converged) all_conv = false;
+  }
+  return all_conv ? AIM_OK : AIM_ENOCONV;
+}
+
+void free_krylov(KrylovWork& K) {
+  void* ps[] = {K.V, K.w, K.wlow, K.ylow, K.r, K.H, K.cs, K.sn, K.g, K.hcol, K.h2, K.part, K.scal, K.active};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  K = KrylovWork{};
+}
+
+int ensure_krylov(aim_op* op, int R, int m, int prec) {
+  KrylovWork& K = op->kw;
+  if (K.V && K.R == R && K.restart >= m && K.prec == prec) return AIM_OK;
+  free_krylov(K);
+  const int64_t n = int64_t(op->ne) * op->N;
+  const int nch = int((n + kChunk - 1) / kChunk);
+  const size_t vb = prec == AIM_FP64 ? sizeof(cplx<double>) : sizeof(cplx<float>);
+  bool ok = true;
+  auto al = [&](void** p, size_t bytes) {
+    if (ok && hipMalloc(p, std::max<size_t>(bytes, 16)) != hipSuccess) {
+      *p = nullptr;
+      ok = false;
+    }
+  };
+  al(&K.V, size_t(m + 1) * R * n * vb);
+  al(reinterpret_cast<void**>(&K.w), sizeof(cplx<double>) * R * n);
+  al(reinterpret_cast<void**>(&K.r), sizeof(cplx<double>) * R * n);
+  if (prec != AIM_FP64) al(&K.ylow, sizeof(cplx<float>) * R * n);
+  al(reinterpret_cast<void**>(&K.H), sizeof(cplx<double>) * R * m * (m + 1));
+  al(reinterpret_cast<void**>(&K.cs), sizeof(cplx<double>) * R * m);
+  al(reinterpret_cast<void**>(&K.sn), sizeof(cplx<double>) * R * m);
+  al(reinterpret_cast<void**>(&K.g), sizeof(cplx<double>) * R * (m + 1));
+  al(reinterpret_cast<void**>(&K.hcol), sizeof(cplx<double>) * R * (m + 1));
+  al(reinterpret_cast<void**>(&K.h2), sizeof(cplx<double>) * R * (m + 1));
+  K.part_len = size_t(R) * (m + 1) * nch * 2;
+  al(reinterpret_cast<void**>(&K.part), sizeof(double) * K.part_len);
+  al(reinterpret_cast<void**>(&K.scal), sizeof(double) * 4 * R);
+  al(reinterpret_cast<void**>(&K.active), sizeof(int) * R);
+  if (!ok) {
+    free_krylov(K);
+    set_error("gmres: device allocation of the Krylov workspace failed");
+    return AIM_ENOMEM;
+  }
+  K.R = R;
+  K.restart = m;
+  K.prec = prec;
+  return AIM_OK;
+}
+
+}  // namespace
+}  // namespace aimm
+
+using namespace aimm;
+
+extern "C" int gmres_solve(aim_op* op, const void* b, void* x, int32_t nrhs, const gmres_opts* opts,
+                           gmres_stat* stats, void* stream) {
+  if (!op || !b || !x || !opts || !stats) {
+    set_error("gmres: NULL argument");
+    return AIM_EINVAL;
+  }
+  if (nrhs < 1 || nrhs > op->R_max) {
+    set_error("gmres: nrhs must be in [1, max_rhs]");
+    return AIM_EINVAL;
+  }
+  if (opts->restart < 1 || opts->restart > 1000 || opts->max_iters < 0 || !(opts->tol > 0) ||
+      (opts->precision != AIM_FP64 && opts->precision != AIM_MIXED)) {
+    set_error("gmres: bad options (restart in [1,1000], max_iters >= 0, tol > 0, precision)");
+    return AIM_EINVAL;
+  }
+  if (b == x) {
+    set_error("gmres: b and x must not alias");
+    return AIM_EINVAL;
+  }
+  if (!op->device_ready || !op->m_set || !op->d_set) {
+    set_error("gmres: device data, macromodels and D must be set");
+    return AIM_ESTATE;
+  }
+  int rc = ensure_krylov(op, nrhs, opts->restart, opts->precision);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (opts->precision == AIM_FP64)
+    return gmres_impl<double>(op, static_cast<const cplx<double>*>(b), static_cast<cplx<double>*>(x), nrhs, *opts,
+                              stats, s);
+  return gmres_impl<float>(op, static_cast<const cplx<double>*>(b), static_cast<cplx<double>*>(x), nrhs, *opts, stats,
+                           s);
+}
+
+namespace aimm {
+void release_krylov(aim_op* op) { free_krylov(op->kw); }
+}  // namespace aimm

@@ -1,0 +1,107 @@
+// The operator object behind the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "aim_kernels.hpp"
+#include "setup.hpp"
+
+struct aim_op;
+
+namespace aimm {
+
+void set_error(const std::string& msg);
+struct KrylovWork;
+
+struct DeviceMem {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+  template <typename T>
+  T* alloc(size_t count) {
+    if (count == 0) count = 1;
+    void* p = nullptr;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) throw std::bad_alloc();
+    ptrs.push_back(p);
+    bytes += count * sizeof(T);
+    return static_cast<T*>(p);
+  }
+  void release(void* p, size_t nbytes) {
+    for (auto& q : ptrs)
+      if (q == p) {
+        (void)hipFree(q);
+        q = nullptr;
+        bytes -= nbytes;
+      }
+  }
+  ~DeviceMem() {
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+  }
+};
+
+// Per-precision copies of the real and complex operator data.
+template <typename T>
+struct PrecData {
+  T* Wp = nullptr;           // [4][N * q3] projection weights, entry = n * q3 + p
+  T* Wt = nullptr;           // [4][q3][N] interpolation weights
+  cplx<T>* near = nullptr;   // pre-corrected near field
+  cplx<T>* gt = nullptr;     // kernel spectrum, [Lx/2+1][Ly/2+1][nz]
+  cplx<T>* tw_x = nullptr;
+  cplx<T>* tw_y = nullptr;
+  cplx<T>* M = nullptr;      // [n_types][N][N] column-major
+  cplx<T>* dval = nullptr;   // D values
+  int B = 1;                 // ky lines per workgroup in the spectrum pass
+};
+
+struct KrylovWork {
+  int R = 0, restart = 0, prec = -1;
+  void* V = nullptr;         // [restart+1][R][n] basis (complex128 or complex64)
+  size_t V_bytes = 0;
+  cplx<double>* w = nullptr; // [R][n] working vector (FP64)
+  void* wlow = nullptr;      // [R][n] low-precision product input/output
+  void* ylow = nullptr;
+  cplx<double>* r = nullptr; // [R][n] residual
+  cplx<double>* H = nullptr; // [R][restart+1][restart]
+  cplx<double>* cs = nullptr;
+  cplx<double>* sn = nullptr;
+  cplx<double>* g = nullptr;  // [R][restart+1]
+  cplx<double>* hcol = nullptr;  // [R][restart+1] first Gram-Schmidt pass
+  cplx<double>* h2 = nullptr;    // [R][restart+1] second pass; least-squares solution
+  double* part = nullptr;     // reduction partials
+  size_t part_len = 0;
+  double* scal = nullptr;     // [R][4] norms / flags
+  int* active = nullptr;      // [R] per-cycle stop column
+};
+
+void release_krylov(aim_op* op);
+
+}  // namespace aimm
+
+struct aim_op {
+  aimm::Setup st;
+  aimm::ArrayIn arr{};
+  std::vector<int32_t> elem_type;
+  std::vector<double> vert;
+  std::vector<int32_t> tri, rwg;
+  int device = 0;
+  int ne = 0, N = 0, R_max = 0, n_types = 0;
+  int Lx = 0, Ly = 0;
+  aimm::FftPlan Px{}, Py{};
+  std::vector<int> type_count, col_start;
+  bool m_set = false, d_set = false;
+  bool device_ready = false;  // false for ops from aim_build_host
+  int64_t d_nnz = 0;
+  size_t lds_max = 65536;
+  aimm::DeviceMem mem;
+  int *sloc = nullptr, *node_ptr = nullptr, *node_ent = nullptr, *near_ptr = nullptr, *near_col = nullptr;
+  int *nbr = nullptr, *d_ptr = nullptr, *d_col = nullptr, *rev_x = nullptr, *rev_y = nullptr, *col_list = nullptr;
+  aimm::PrecData<double> p64;
+  aimm::PrecData<float> p32;
+  void* u = nullptr;      // [R][n] macromodel output (sized for complex128)
+  void* grid = nullptr;   // Q / Phi (sized for complex128)
+  void* S = nullptr;      // spectrum pass buffer (sized for complex128)
+  aimm::KrylovWork kw;
+};

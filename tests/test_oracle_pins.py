@@ -276,6 +276,14 @@ def test_translation_invariance_of_near_blocks():
     assert abs(a.C - b.C).max() < 1e-13 * abs(a.C).max()
 
 
+def test_near_blocks_applied_by_offset_equal_global_matrix():
+    """The per-offset application used for large arrays equals the global sparse matrix."""
+    wl = make_workload(2, px=6, py=5, nrhs=1)
+    op = OracleOperator(wl)
+    u = op.macro_apply(wl.test_vectors(1)[0])
+    assert _rel(op.near_apply(u, by_blocks=True), op.C @ u) < 1e-14
+
+
 def test_near_pairs_are_exact_galerkin(op0, dense0):
     """On near pairs the AIM operator reproduces the Galerkin entry (pre-correction)."""
     nb = op0.nb
