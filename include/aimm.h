@@ -133,9 +133,9 @@ int aim_matvec(aim_op* op, const void* x, void* y, int32_t nrhs, int32_t precisi
 /* Kernel timing of the full product with HIP events on `stream`: one warm-up, then
  * reps products; ms[k] receives the mean duration in milliseconds of kernel k:
  * 0 macromodel GEMM, 1 projection (step (i)), 2 forward FFT along y, 3 FFT along x
- * with the kernel-spectrum product, 4 inverse FFT along y (steps (ii)), 5
- * interpolation (step (iii)) fused with the near field and D.  ms: host [6].
- * Synchronises the stream. */
+ * with the kernel-spectrum product, 4 inverse FFT along y (step (ii)), 5 pre-corrected
+ * near field, 6 interpolation (step (iii)) fused with D and the final combination.
+ * ms: host [7].  Synchronises the stream. */
 int aim_time_kernels(aim_op* op, const void* x, void* y, int32_t nrhs, int32_t precision,
                      int32_t reps, double* ms, void* stream);
 

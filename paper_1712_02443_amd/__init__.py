@@ -125,13 +125,13 @@ class AimOperator:
         check(self.lib.aim_matvec(self._op, _dev_ptr(x), _dev_ptr(y), R, precision, flags, _stream(self._torch, stream)))
         return y
 
-    KERNELS = ("macro_gemm", "project", "fft_y_fwd", "fft_x_conv", "fft_y_inv", "interp_near_d")
+    KERNELS = ("macro_gemm", "project", "fft_y_fwd", "fft_x_conv", "fft_y_inv", "near_field", "interp_d")
 
     def time_kernels(self, x, precision=AIM_FP64, reps=20, stream=None) -> dict:
         """Mean per-kernel duration (ms) of the full product, from HIP events on the stream."""
         R = self._check_vec(x, precision)
         y = self._torch.empty_like(x)
-        ms = np.zeros(6)
+        ms = np.zeros(7)
         check(self.lib.aim_time_kernels(self._op, _dev_ptr(x), _dev_ptr(y), R, precision, int(reps),
                                         ms.ctypes.data_as(_lib._f64p), _stream(self._torch, stream)))
         return dict(zip(self.KERNELS, ms.tolist()))

@@ -10,41 +10,73 @@
 
 namespace aimm {
 
-// ---- step (i): projection, one thread per grid node, deterministic gather --------
+// ---- step (i): projection, owner-computes gather --------------------------------
+// Grid node g is written by exactly one element (its owner: the element whose
+// pitch-wide home cell contains g, the last row/column owning the tail).  The owner
+// gathers every basis of itself and of the neighbours whose stencil box covers g.
+// Lanes of a wave are 64 consecutive elements at the same element-local node, so
+// the gather table row is wave-uniform and u is read from its element-fastest copy.
 template <typename T>
-__global__ void __launch_bounds__(256) k_project(const cplx<T>* __restrict__ u, cplx<T>* __restrict__ Q,
+__global__ void __launch_bounds__(256) k_project(const cplx<T>* __restrict__ uT, cplx<T>* __restrict__ Q,
                                                  ProjArgs a, const T* __restrict__ Wp) {
-  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  const int ne64 = (a.ne + 63) & ~63;
+  const int nloc = a.ex * a.ey * a.ez;
   const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (gid >= nodes * a.R) return;
-  const int r = int(gid / nodes);
-  const int64_t g = gid - int64_t(r) * nodes;
-  const int gz = int(g % a.nz);
-  const int gy = int((g / a.nz) % a.ny);
-  const int gx = int(g / (int64_t(a.nz) * a.ny));
-  cplx<T> acc[4];
-  for (int p = 0; p < 4; ++p) acc[p] = cmk<T>(0, 0);
-  const int tx = gx - (a.ex - 1), ty = gy - (a.ey - 1);
-  const int ix_lo = tx <= 0 ? 0 : (tx + a.pitch - 1) / a.pitch;
-  const int iy_lo = ty <= 0 ? 0 : (ty + a.pitch - 1) / a.pitch;
-  const int ix_hi = min(a.px - 1, gx / a.pitch);
-  const int iy_hi = min(a.py - 1, gy / a.pitch);
+  const int m = int(gid % ne64);
+  const int64_t rest = gid / ne64;
+  const int L = __builtin_amdgcn_readfirstlane(int(rest % nloc));
+  const int r = __builtin_amdgcn_readfirstlane(int(rest / nloc));
+  if (r >= a.R || m >= a.ne) return;
+  const int lz = L % a.ez, ly = (L / a.ez) % a.ey, lx = L / (a.ez * a.ey);
+  const int ix = m % a.px, iy = m / a.px;
+  if (!((lx < a.pitch || ix == a.px - 1) && (ly < a.pitch || iy == a.py - 1))) return;
   const int64_t NQ = int64_t(a.N) * a.q3;
-  for (int iy = iy_lo; iy <= iy_hi; ++iy) {
-    for (int ix = ix_lo; ix <= ix_hi; ++ix) {
-      const int lx = gx - ix * a.pitch, ly = gy - iy * a.pitch;
-      const int node = (lx * a.ey + ly) * a.ez + gz;
+  cplx<T> acc[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) acc[p] = cmk<T>(0, 0);
+  const cplx<T>* ur = uT + int64_t(r) * a.N * a.ne;
+  for (int dy = 0; ly + a.pitch * dy < a.ey; ++dy) {
+    for (int dx = 0; lx + a.pitch * dx < a.ex; ++dx) {
+      const int node = ((lx + a.pitch * dx) * a.ey + (ly + a.pitch * dy)) * a.ez + lz;
       const int e0 = a.node_ptr[node], e1 = a.node_ptr[node + 1];
-      const cplx<T>* ue = u + (int64_t(r) * a.ne + int64_t(iy) * a.px + ix) * a.N;
+      const bool ok = ix - dx >= 0 && iy - dy >= 0;
+      const int ms = m - dx - dy * a.px;
       for (int e = e0; e < e1; ++e) {
         const int ent = a.node_ent[e];
-        const cplx<T> v = ue[ent / a.q3];
+        const int n = a.node_n[e];
+        const cplx<T> v = ok ? ur[int64_t(n) * a.ne + ms] : cmk<T>(0, 0);
+#pragma unroll
         for (int p = 0; p < 4; ++p) cfmas(acc[p], Wp[p * NQ + ent], v);
       }
     }
   }
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  const int64_t g = (int64_t(ix * a.pitch + lx) * a.ny + (iy * a.pitch + ly)) * a.nz + lz;
   cplx<T>* out = Q + int64_t(r) * 4 * nodes + g;
+#pragma unroll
   for (int p = 0; p < 4; ++p) out[p * nodes] = acc[p];
+}
+
+// [R][ne][N] -> [R][N][ne] (element-fastest copy of a vector); with the extents
+// swapped it maps [R][N][ne] back to [R][ne][N]
+template <typename T>
+__global__ void __launch_bounds__(256) k_transpose(const cplx<T>* __restrict__ x, cplx<T>* __restrict__ xT, int ne,
+                                                   int N) {
+  __shared__ cplx<T> tile[32][33];
+  const int r = blockIdx.z;
+  const int n0 = blockIdx.x * 32, m0 = blockIdx.y * 32;
+  const cplx<T>* src = x + int64_t(r) * ne * N;
+  cplx<T>* dst = xT + int64_t(r) * ne * N;
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+  for (int k = ty; k < 32; k += 8) {
+    const int m = m0 + k, n = n0 + tx;
+    if (m < ne && n < N) tile[k][tx] = src[int64_t(m) * N + n];
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int n = n0 + k, m = m0 + tx;
+    if (m < ne && n < N) dst[int64_t(n) * ne + m] = tile[tx][k];
+  }
 }
 
 // ---- step (ii), pass 1: forward FFT along y of every (r, psi, x) plane ------------
@@ -166,115 +198,283 @@ __global__ void __launch_bounds__(256) k_fft_y_inv(const cplx<T>* in, cplx<T>* o
   }
 }
 
-// ---- step (iii) + near field + D: one thread per (r, element, RWG) row -----------
-template <typename T, int MODE>
-__global__ void __launch_bounds__(256) k_interp_combine(const cplx<T>* __restrict__ Phi,
-                                                        const cplx<T>* __restrict__ u,
-                                                        const cplx<T>* __restrict__ x, cplx<T>* __restrict__ y,
-                                                        CombineArgs a, const T* __restrict__ Wt,
-                                                        const cplx<T>* __restrict__ near_val,
-                                                        const cplx<T>* __restrict__ d_val) {
-  const int64_t rows = int64_t(a.ne) * a.N;
-  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (gid >= rows * a.R) return;
-  const int r = int(gid / rows);
-  const int64_t mn = gid - int64_t(r) * rows;
-  const int m = int(mn / a.N), n = int(mn - int64_t(m) * a.N);
+// ---- pre-corrected near field: nf = C u ----------------------------------------
+// Lanes are 64 consecutive elements, a wave walks one CSR row n of the shared
+// near-field block (wave-uniform entries), u is read element-fastest.  Results are
+// staged in LDS and written element-major.
+constexpr int kNearRows = 16;
+template <typename T>
+__global__ void __launch_bounds__(256) k_near(const cplx<T>* __restrict__ uT, cplx<T>* __restrict__ nf, NearArgs a,
+                                              const cplx<T>* __restrict__ near_val) {
+  __shared__ cplx<T> tile[kNearRows][65];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int n0 = blockIdx.x * kNearRows, m0 = blockIdx.y * 64, r = blockIdx.z;
+  const int m = m0 + lane;
+  const bool valid = m < a.ne;
   const int ix = m % a.px, iy = m / a.px;
-  const int gx = ix * a.pitch + a.sloc[3 * n], gy = iy * a.pitch + a.sloc[3 * n + 1], gz = a.sloc[3 * n + 2];
+  const cplx<T>* ur = uT + int64_t(r) * a.N * a.ne;
+  constexpr int U = 8;  // entries in flight per lane
+  for (int rr = wave; rr < kNearRows; rr += 4) {
+    const int n = __builtin_amdgcn_readfirstlane(n0 + rr);
+    cplx<T> acc = cmk<T>(0, 0);
+    if (n < a.N) {
+      const int e0 = a.near_ptr[n], e1 = a.near_ptr[n + 1];
+      int e = e0;
+      for (; e + U <= e1; e += U) {
+        cplx<T> uv[U], cv[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+          const int c = a.near_col[e + k];
+          const int o = c >> 16, np_ = c & 0xFFFF;
+          const int jx = ix + a.offsets[2 * o], jy = iy + a.offsets[2 * o + 1];
+          const bool ok = valid && jx >= 0 && jx < a.px && jy >= 0 && jy < a.py;
+          cv[k] = near_val[e + k];
+          uv[k] = ok ? ur[int64_t(np_) * a.ne + jy * a.px + jx] : cmk<T>(0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) cfma(acc, cv[k], uv[k]);
+      }
+      for (; e < e1; ++e) {
+        const int c = a.near_col[e];
+        const int o = c >> 16, np_ = c & 0xFFFF;
+        const int jx = ix + a.offsets[2 * o], jy = iy + a.offsets[2 * o + 1];
+        if (valid && jx >= 0 && jx < a.px && jy >= 0 && jy < a.py)
+          cfma(acc, near_val[e], ur[int64_t(np_) * a.ne + jy * a.px + jx]);
+      }
+    }
+    tile[rr][lane] = acc;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < 64 * kNearRows; idx += 256) {
+    const int mm = idx / kNearRows, nn = idx - mm * kNearRows;
+    if (m0 + mm < a.ne && n0 + nn < a.N) nf[(int64_t(r) * a.ne + m0 + mm) * a.N + n0 + nn] = tile[nn][mm];
+  }
+}
+
+// ---- step (iii) + combine: one workgroup per tile of elements ---------------------
+// The tile's box of grid potentials (4 psi) is staged in LDS; every basis gathers its
+// (N_O+1)^3 nodes per psi from LDS.  MODE 0: y = D x - (v + nf); 1: y = v + nf;
+// 2: y = v, with v = -j k eta0 [sum_{x,y,z} I_psi Phi_psi - k^-2 I_phi Phi_phi].
+template <typename T, int MODE, int QS>
+__global__ void __launch_bounds__(256) k_interp(const cplx<T>* __restrict__ Phi, const cplx<T>* __restrict__ nf,
+                                                const cplx<T>* __restrict__ x, cplx<T>* __restrict__ y, InterpArgs a,
+                                                const T* __restrict__ Wt, const cplx<T>* __restrict__ d_val) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* box = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int ntx = (a.px + a.TX - 1) / a.TX;
+  const int tile = blockIdx.x, r = blockIdx.y;
+  const int ix0 = (tile % ntx) * a.TX, iy0 = (tile / ntx) * a.TY;
+  const int gx0 = ix0 * a.pitch, gy0 = iy0 * a.pitch;
+  const int bx = min(a.pitch * (a.TX - 1) + a.ex, a.nx - gx0);
+  const int by = min(a.pitch * (a.TY - 1) + a.ey, a.ny - gy0);
+  const int bz = a.nz;
   const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
   const cplx<T>* ph = Phi + int64_t(r) * 4 * nodes;
-  cplx<T> acc = cmk<T>(0, 0);
-  for (int p = 0; p < 4; ++p) {
-    cplx<T> s = cmk<T>(0, 0);
-    const T* w = Wt + int64_t(p) * a.q3 * a.N + n;
-    const cplx<T>* f = ph + p * nodes;
-    int idx = 0;
-    for (int i = 0; i < a.q; ++i)
-      for (int j = 0; j < a.q; ++j) {
-        const cplx<T>* fr = f + (int64_t(gx + i) * a.ny + (gy + j)) * a.nz + gz;
-        for (int l = 0; l < a.q; ++l, ++idx) cfmas(s, w[int64_t(idx) * a.N], fr[l]);
+  const int run = by * bz;  // contiguous run per (psi, x)
+  for (int idx = threadIdx.x; idx < 4 * bx * run; idx += blockDim.x) {
+    const int p = idx / (bx * run);
+    const int rem = idx - p * bx * run;
+    const int lx = rem / run, k = rem - lx * run;
+    box[idx] = ph[p * nodes + (int64_t(gx0 + lx) * a.ny + gy0) * a.nz + k];
+  }
+  __syncthreads();
+  constexpr int q = QS, q3 = QS * QS * QS;
+  const int64_t rows = int64_t(a.ne) * a.N;
+  for (int ty = 0; ty < a.TY; ++ty) {
+    const int iy = iy0 + ty;
+    if (iy >= a.py) break;
+    for (int tx = 0; tx < a.TX; ++tx) {
+      const int ix = ix0 + tx;
+      if (ix >= a.px) break;
+      const int m = iy * a.px + ix;
+      const int64_t rowbase = int64_t(r) * rows + int64_t(m) * a.N;
+#pragma unroll 1
+      for (int n = threadIdx.x; n < a.N; n += blockDim.x) {
+        const int ox = tx * a.pitch + a.sloc[3 * n], oy = ty * a.pitch + a.sloc[3 * n + 1], oz = a.sloc[3 * n + 2];
+        cplx<T> dx = cmk<T>(0, 0);
+        if (MODE == 0) {
+          const cplx<T>* xr = x + rowbase;
+          for (int e = a.d_ptr[n]; e < a.d_ptr[n + 1]; ++e) cfma(dx, d_val[e], xr[a.d_col[e]]);
+        }
+        cplx<T> acc = cmk<T>(0, 0);
+#pragma unroll 1
+        for (int p = 0; p < 4; ++p) {
+          cplx<T> sacc = cmk<T>(0, 0);
+          const T* w = Wt + int64_t(p) * q3 * a.N + n;
+          const cplx<T>* f = box + p * bx * run;
+#pragma unroll
+          for (int i = 0; i < q; ++i)
+#pragma unroll
+            for (int j = 0; j < q; ++j) {
+              const cplx<T>* fr = f + ((ox + i) * by + (oy + j)) * bz + oz;
+#pragma unroll
+              for (int l = 0; l < q; ++l) cfmas(sacc, w[int64_t((i * q + j) * q + l) * a.N], fr[l]);
+            }
+          cfmas(acc, p < 3 ? T(1) : T(a.sig_phi), sacc);
+        }
+        cplx<T> out = cmk<T>(T(a.keta) * acc.im, -T(a.keta) * acc.re);  // -j k eta0 * acc
+        if (MODE != 2) out = cadd(out, nf[rowbase + n]);
+        if (MODE == 0) out = csub(dx, out);
+        y[rowbase + n] = out;
       }
-    cfmas(acc, p < 3 ? T(1) : T(a.sig_phi), s);
-  }
-  // far field: -j k eta * acc
-  cplx<T> out = cmk<T>(T(a.keta) * acc.im, -T(a.keta) * acc.re);
-  if (MODE != 2) {  // + C u (pre-corrected near field)
-    const cplx<T>* ur = u + int64_t(r) * rows;
-    const int* nb = a.nbr + int64_t(m) * a.n_off;
-    cplx<T> nf = cmk<T>(0, 0);
-    for (int e = a.near_ptr[n]; e < a.near_ptr[n + 1]; ++e) {
-      const int c = a.near_col[e];
-      const int o = c / a.N, np_ = c - o * a.N;
-      const int mm = nb[o];
-      if (mm >= 0) cfma(nf, near_val[e], ur[int64_t(mm) * a.N + np_]);
     }
-    out = cadd(out, nf);
   }
-  if (MODE == 0) {  // y = D x - G u
-    const cplx<T>* xr = x + int64_t(r) * rows + int64_t(m) * a.N;
-    cplx<T> dx = cmk<T>(0, 0);
-    for (int e = a.d_ptr[n]; e < a.d_ptr[n + 1]; ++e) cfma(dx, d_val[e], xr[a.d_col[e]]);
-    out = csub(dx, out);
-  }
-  y[gid] = out;
 }
 
 // ---- section III: block-diagonal macromodel product, grouped complex GEMM --------
-// U[:, c] = M_t X[:, c] for every column c = r * n_elem + m of an element of kind t.
+// U[:, c] = M_t X[:, c] for every column c = r * n_elem + m of an element of kind t,
+// on the matrix cores: each complex step is four real MFMAs (re*re - im*im,
+// re*im + im*re).  A 64 x 64 output tile per workgroup (2 x 2 waves); M_t and X
+// tiles are staged in LDS; the output is written element-fastest, uT[r][i][m].
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_macro_gemm(const cplx<T>* __restrict__ M, const cplx<T>* __restrict__ X,
-                                                    cplx<T>* __restrict__ U, GemmArgs a) {
-  constexpr int TM = 64, TN = 64, TK = 16;
-  __shared__ cplx<T> As[TK][TM];
-  __shared__ cplx<T> Bs[TK][TN + 1];
-  __shared__ int cols[TN];
-  // which kind and which column tile
-  int t = 0, tile = blockIdx.x;
+__device__ __forceinline__ void gemm_tile_setup(const GemmArgs& a, int& t, int& c0, int* cols, int64_t* colbase) {
+  t = 0;
+  int tile = blockIdx.x;
   while (t + 1 < a.n_types && tile >= a.tile_start[t + 1]) ++t;
   tile -= a.tile_start[t];
+  c0 = tile * 64;
   const int ncols = a.R * a.type_count[t];
-  const int c0 = tile * TN;
-  const int i0 = blockIdx.y * TM;
-  const int N = a.N;
-  const cplx<T>* Mt = M + int64_t(t) * N * N;
-  if (threadIdx.x < TN) {
+  if (threadIdx.x < 64) {
     const int c = c0 + threadIdx.x;
-    cols[threadIdx.x] = c < ncols ? a.col_list[a.col_start[t] + c] : -1;
+    const int col = c < ncols ? a.col_list[a.col_start[t] + c] : -1;
+    cols[threadIdx.x] = col;
+    colbase[threadIdx.x] = col < 0 ? -1 : int64_t(col / a.ne) * a.N * a.ne + (col % a.ne);
   }
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  cplx<T> acc[4][4];
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) acc[i][j] = cmk<T>(0, 0);
+}
+
+template <typename T, int KT>
+__device__ __forceinline__ void gemm_load_tiles(const cplx<T>* Mt, const cplx<T>* X, int N, int i0, int k0,
+                                                const int* cols, cplx<T>* As, cplx<T>* Bs) {
+  for (int e = threadIdx.x; e < KT * 64; e += 256) {
+    const int k = e / 64, i = e - k * 64;
+    As[k * 64 + i] = (i0 + i < N && k0 + k < N) ? Mt[int64_t(k0 + k) * N + i0 + i] : cmk<T>(0, 0);
+  }
+  for (int e = threadIdx.x; e < KT * 64; e += 256) {
+    const int j = e / KT, k = e - j * KT;
+    const int c = cols[j];
+    Bs[k * 64 + j] = (c >= 0 && k0 + k < N) ? X[int64_t(c) * N + k0 + k] : cmk<T>(0, 0);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void gemm_store_rows(cplx<T>* U, const cplx<T>* Ct, int ldc, const int64_t* colbase, int N,
+                                                int ne, int row0, int nrows) {
+  const int jc = threadIdx.x % 64;
+  const int64_t cb = colbase[jc];
+  for (int rr = threadIdx.x / 64; rr < nrows; rr += 4) {
+    const int gi = row0 + rr;
+    if (cb >= 0 && gi < N) U[cb + int64_t(gi) * ne] = Ct[rr * ldc + jc];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_gemm_f32(const cplx<float>* __restrict__ M, const cplx<float>* __restrict__ X,
+                                                  cplx<float>* __restrict__ U, GemmArgs a) {
+  constexpr int KT = 32;
+  __shared__ __align__(16) cplx<float> smem[2 * KT * 64];
+  __shared__ int cols[64];
+  __shared__ int64_t colbase[64];
+  cplx<float>* As = smem;
+  cplx<float>* Bs = smem + KT * 64;
+  int t, c0;
+  gemm_tile_setup<float>(a, t, c0, cols, colbase);
+  const int N = a.N, i0 = blockIdx.y * 64;
+  const cplx<float>* Mt = M + int64_t(t) * N * N;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wi = wave & 1, wj = wave >> 1;
+  f32x16 accR = {}, accI = {};
   __syncthreads();
-  for (int k0 = 0; k0 < N; k0 += TK) {
-    for (int e = threadIdx.x; e < TK * TM; e += 256) {
-      const int kk = e / TM, ii = e - kk * TM;
-      const int gi = i0 + ii, gk = k0 + kk;
-      As[kk][ii] = (gi < N && gk < N) ? Mt[int64_t(gk) * N + gi] : cmk<T>(0, 0);
-    }
-    for (int e = threadIdx.x; e < TK * TN; e += 256) {
-      const int jj = e / TK, kk = e - jj * TK;
-      const int c = cols[jj], gk = k0 + kk;
-      Bs[kk][jj] = (c >= 0 && gk < N) ? X[int64_t(c) * N + gk] : cmk<T>(0, 0);
-    }
+  for (int k0 = 0; k0 < N; k0 += KT) {
+    gemm_load_tiles<float, KT>(Mt, X, N, i0, k0, cols, As, Bs);
     __syncthreads();
-    for (int kk = 0; kk < TK; ++kk) {
-      cplx<T> av[4], bv[4];
-      for (int i = 0; i < 4; ++i) av[i] = As[kk][tx + 16 * i];
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][ty + 16 * j];
-      for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) cfma(acc[i][j], av[i], bv[j]);
+#pragma unroll 4
+    for (int kk = 0; kk < KT; kk += 2) {
+      const int k = kk + (lane >> 5);
+      const cplx<float> av = As[k * 64 + wi * 32 + (lane & 31)];
+      const cplx<float> bv = Bs[k * 64 + wj * 32 + (lane & 31)];
+      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(av.re, bv.re, accR, 0, 0, 0);
+      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(-av.im, bv.im, accR, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(av.re, bv.im, accI, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(av.im, bv.re, accI, 0, 0, 0);
     }
     __syncthreads();
   }
-  for (int j = 0; j < 4; ++j) {
-    const int c = cols[ty + 16 * j];
-    if (c < 0) continue;
-    for (int i = 0; i < 4; ++i) {
-      const int gi = i0 + tx + 16 * i;
-      if (gi < N) U[int64_t(c) * N + gi] = acc[i][j];
+  cplx<float>* Ct = smem;  // [32][65]
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();
+    if (wi == h) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);  // v_mfma_f32_32x32x2f32 output row
+        const int j = wj * 32 + (lane & 31);
+        Ct[i * 65 + j] = cmk<float>(accR[r], accI[r]);
+      }
     }
+    __syncthreads();
+    gemm_store_rows<float>(U, Ct, 65, colbase, N, a.ne, i0 + 32 * h, 32);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_gemm_f64(const cplx<double>* __restrict__ M,
+                                                  const cplx<double>* __restrict__ X, cplx<double>* __restrict__ U,
+                                                  GemmArgs a) {
+  constexpr int KT = 16;
+  __shared__ __align__(16) cplx<double> smem[2 * KT * 64];
+  __shared__ int cols[64];
+  __shared__ int64_t colbase[64];
+  cplx<double>* As = smem;
+  cplx<double>* Bs = smem + KT * 64;
+  int t, c0;
+  gemm_tile_setup<double>(a, t, c0, cols, colbase);
+  const int N = a.N, i0 = blockIdx.y * 64;
+  const cplx<double>* Mt = M + int64_t(t) * N * N;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wi = wave & 1, wj = wave >> 1;
+  f64x4 accR[2][2] = {}, accI[2][2] = {};
+  __syncthreads();
+  for (int k0 = 0; k0 < N; k0 += KT) {
+    gemm_load_tiles<double, KT>(Mt, X, N, i0, k0, cols, As, Bs);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KT; kk += 4) {
+      const int k = kk + (lane >> 4);
+      cplx<double> av[2], bv[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        av[q] = As[k * 64 + wi * 32 + q * 16 + (lane & 15)];
+        bv[q] = Bs[k * 64 + wj * 32 + q * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) {
+          accR[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti].re, bv[tj].re, accR[ti][tj], 0, 0, 0);
+          accR[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[ti].im, bv[tj].im, accR[ti][tj], 0, 0, 0);
+          accI[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti].re, bv[tj].im, accI[ti][tj], 0, 0, 0);
+          accI[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti].im, bv[tj].re, accI[ti][tj], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  cplx<double>* Ct = smem;  // [32][64]
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();
+    if (wi == h) {
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = ti * 16 + (lane >> 4) + 4 * r;  // v_mfma_f64_16x16x4f64 output row
+            const int j = wj * 32 + tj * 16 + (lane & 15);
+            Ct[i * 64 + j] = cmk<double>(accR[ti][tj][r], accI[ti][tj][r]);
+          }
+    }
+    __syncthreads();
+    gemm_store_rows<double>(U, Ct, 64, colbase, N, a.ne, i0 + 32 * h, 32);
   }
 }
 
@@ -342,9 +542,16 @@ __global__ void k_convert(const cplx<Tin>* in, cplx<Tout>* out, int64_t n) {
 static inline unsigned blocks_for(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
 
 template <typename T>
-hipError_t launch_project(const cplx<T>* u, cplx<T>* Q, const ProjArgs& a, const T* Wp, hipStream_t s) {
-  const int64_t n = int64_t(a.nx) * a.ny * a.nz * a.R;
-  hipLaunchKernelGGL(k_project<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, u, Q, a, Wp);
+hipError_t launch_project(const cplx<T>* uT, cplx<T>* Q, const ProjArgs& a, const T* Wp, hipStream_t s) {
+  const int64_t ne64 = (a.ne + 63) / 64 * 64;
+  const int64_t n = ne64 * a.ex * a.ey * a.ez * a.R;
+  hipLaunchKernelGGL(k_project<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, uT, Q, a, Wp);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_transpose(const cplx<T>* x, cplx<T>* xT, int R, int ne, int N, hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose<T>, dim3((N + 31) / 32, (ne + 31) / 32, R), dim3(256), 0, s, x, xT, ne, N);
   return hipGetLastError();
 }
 
@@ -373,17 +580,34 @@ hipError_t launch_convolve(const cplx<T>* Q, cplx<T>* Phi, cplx<T>* S, const Con
 }
 
 template <typename T>
-hipError_t launch_combine(int mode, const cplx<T>* Phi, const cplx<T>* u, const cplx<T>* x, cplx<T>* y,
-                          const CombineArgs& a, const T* Wt, const cplx<T>* near_val, const cplx<T>* d_val,
-                          hipStream_t s) {
-  const int64_t n = int64_t(a.ne) * a.N * a.R;
-  const dim3 g(blocks_for(n, 256)), b(256);
-  if (mode == 0)
-    hipLaunchKernelGGL((k_interp_combine<T, 0>), g, b, 0, s, Phi, u, x, y, a, Wt, near_val, d_val);
-  else if (mode == 1)
-    hipLaunchKernelGGL((k_interp_combine<T, 1>), g, b, 0, s, Phi, u, x, y, a, Wt, near_val, d_val);
-  else
-    hipLaunchKernelGGL((k_interp_combine<T, 2>), g, b, 0, s, Phi, u, x, y, a, Wt, near_val, d_val);
+hipError_t launch_near(const cplx<T>* uT, cplx<T>* nf, const NearArgs& a, const cplx<T>* near_val, hipStream_t s) {
+  const dim3 g((a.N + kNearRows - 1) / kNearRows, (a.ne + 63) / 64, a.R);
+  hipLaunchKernelGGL(k_near<T>, g, dim3(256), 0, s, uT, nf, a, near_val);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_interp(int mode, const cplx<T>* Phi, const cplx<T>* nf, const cplx<T>* x, cplx<T>* y,
+                         const InterpArgs& a, const T* Wt, const cplx<T>* d_val, hipStream_t s) {
+  const int tiles = ((a.px + a.TX - 1) / a.TX) * ((a.py + a.TY - 1) / a.TY);
+  const size_t lds = interp_lds_bytes(a, sizeof(cplx<T>));
+  const dim3 g(tiles, a.R), b(256);
+#define AIM_INTERP(M, QQ) hipLaunchKernelGGL((k_interp<T, M, QQ>), g, b, lds, s, Phi, nf, x, y, a, Wt, d_val)
+#define AIM_INTERP_Q(M)                  \
+  switch (a.q) {                        \
+    case 2: AIM_INTERP(M, 2); break;    \
+    case 3: AIM_INTERP(M, 3); break;    \
+    default: AIM_INTERP(M, 4); break;   \
+  }
+  if (mode == 0) {
+    AIM_INTERP_Q(0)
+  } else if (mode == 1) {
+    AIM_INTERP_Q(1)
+  } else {
+    AIM_INTERP_Q(2)
+  }
+#undef AIM_INTERP_Q
+#undef AIM_INTERP
   return hipGetLastError();
 }
 
@@ -391,7 +615,13 @@ template <typename T>
 hipError_t launch_macro(const cplx<T>* M, const cplx<T>* X, cplx<T>* U, const GemmArgs& a, hipStream_t s) {
   const int tiles = a.tile_start[a.n_types];  // host copy of the tile prefix sums
   if (tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_macro_gemm<T>, dim3(tiles, (a.N + 63) / 64), dim3(256), 0, s, M, X, U, a);
+  const dim3 g(tiles, (a.N + 63) / 64), b(256);
+  if constexpr (sizeof(T) == sizeof(float))
+    hipLaunchKernelGGL(k_gemm_f32, g, b, 0, s, reinterpret_cast<const cplx<float>*>(M),
+                       reinterpret_cast<const cplx<float>*>(X), reinterpret_cast<cplx<float>*>(U), a);
+  else
+    hipLaunchKernelGGL(k_gemm_f64, g, b, 0, s, reinterpret_cast<const cplx<double>*>(M),
+                       reinterpret_cast<const cplx<double>*>(X), reinterpret_cast<cplx<double>*>(U), a);
   return hipGetLastError();
 }
 
@@ -448,6 +678,24 @@ hipError_t configure_lds(size_t bytes) {
   AIM_ATTR((k_fft_x<float, 0>))
   AIM_ATTR((k_fft_x<double, 0>))
   AIM_ATTR((k_fft_x<double, 1>))
+  AIM_ATTR((k_interp<float, 0, 2>))
+  AIM_ATTR((k_interp<float, 0, 3>))
+  AIM_ATTR((k_interp<float, 0, 4>))
+  AIM_ATTR((k_interp<float, 1, 2>))
+  AIM_ATTR((k_interp<float, 1, 3>))
+  AIM_ATTR((k_interp<float, 1, 4>))
+  AIM_ATTR((k_interp<float, 2, 2>))
+  AIM_ATTR((k_interp<float, 2, 3>))
+  AIM_ATTR((k_interp<float, 2, 4>))
+  AIM_ATTR((k_interp<double, 0, 2>))
+  AIM_ATTR((k_interp<double, 0, 3>))
+  AIM_ATTR((k_interp<double, 0, 4>))
+  AIM_ATTR((k_interp<double, 1, 2>))
+  AIM_ATTR((k_interp<double, 1, 3>))
+  AIM_ATTR((k_interp<double, 1, 4>))
+  AIM_ATTR((k_interp<double, 2, 2>))
+  AIM_ATTR((k_interp<double, 2, 3>))
+  AIM_ATTR((k_interp<double, 2, 4>))
 #undef AIM_ATTR
   return e;
 }
@@ -459,12 +707,17 @@ template hipError_t launch_convolve<float>(const cplx<float>*, cplx<float>*, cpl
                                            hipEvent_t*);
 template hipError_t launch_convolve<double>(const cplx<double>*, cplx<double>*, cplx<double>*, const ConvArgs&,
                                             hipStream_t, hipEvent_t*);
-template hipError_t launch_combine<float>(int, const cplx<float>*, const cplx<float>*, const cplx<float>*, cplx<float>*,
-                                          const CombineArgs&, const float*, const cplx<float>*, const cplx<float>*,
+template hipError_t launch_near<float>(const cplx<float>*, cplx<float>*, const NearArgs&, const cplx<float>*,
+                                       hipStream_t);
+template hipError_t launch_near<double>(const cplx<double>*, cplx<double>*, const NearArgs&, const cplx<double>*,
+                                        hipStream_t);
+template hipError_t launch_interp<float>(int, const cplx<float>*, const cplx<float>*, const cplx<float>*, cplx<float>*,
+                                         const InterpArgs&, const float*, const cplx<float>*, hipStream_t);
+template hipError_t launch_interp<double>(int, const cplx<double>*, const cplx<double>*, const cplx<double>*,
+                                          cplx<double>*, const InterpArgs&, const double*, const cplx<double>*,
                                           hipStream_t);
-template hipError_t launch_combine<double>(int, const cplx<double>*, const cplx<double>*, const cplx<double>*,
-                                           cplx<double>*, const CombineArgs&, const double*, const cplx<double>*,
-                                           const cplx<double>*, hipStream_t);
+template hipError_t launch_transpose<float>(const cplx<float>*, cplx<float>*, int, int, int, hipStream_t);
+template hipError_t launch_transpose<double>(const cplx<double>*, cplx<double>*, int, int, int, hipStream_t);
 template hipError_t launch_macro<float>(const cplx<float>*, const cplx<float>*, cplx<float>*, const GemmArgs&,
                                         hipStream_t);
 template hipError_t launch_macro<double>(const cplx<double>*, const cplx<double>*, cplx<double>*, const GemmArgs&,

@@ -11,12 +11,15 @@ namespace aimm {
 constexpr int kMaxNz = 16;     // grid nodes along z (direct aperiodic sum in the spectrum pass)
 constexpr int kMaxTypes = 16;  // distinct element kinds
 
+constexpr int kMaxOffsets = 25;  // lattice offsets carrying near-field pairs
+
 struct ProjArgs {
   int R, ne, N, px, py, pitch;
   int ex, ey, ez;
   int nx, ny, nz, q3;
   const int* node_ptr;
   const int* node_ent;
+  const int* node_n;
 };
 
 struct ConvArgs {
@@ -29,21 +32,30 @@ struct ConvArgs {
   const int* rev_y;
 };
 
-struct CombineArgs {
-  int R, ne, N, px, pitch;
-  int nx, ny, nz, q, q3;
-  int n_off;
-  double keta, sig_phi;
-  const int* sloc;
+struct NearArgs {
+  int R, ne, N, px, py;
+  const int* offsets;  // [n_off][2] (dx, dy)
   const int* near_ptr;
   const int* near_col;
-  const int* nbr;
+};
+
+struct InterpArgs {
+  int R, ne, N, px, py, pitch;
+  int nx, ny, nz, q, q3, ex, ey;
+  int TX, TY;  // elements per workgroup tile
+  double keta, sig_phi;
+  const int* sloc;
   const int* d_ptr;
   const int* d_col;
 };
 
+inline size_t interp_lds_bytes(const InterpArgs& a, size_t elem) {
+  const size_t bx = size_t(a.pitch) * (a.TX - 1) + a.ex, by = size_t(a.pitch) * (a.TY - 1) + a.ey;
+  return 4 * bx * by * a.nz * elem;
+}
+
 struct GemmArgs {
-  int N, R, n_types;
+  int N, R, n_types, ne;
   int tile_start[kMaxTypes + 1];
   int type_count[kMaxTypes];
   int col_start[kMaxTypes];
@@ -51,14 +63,17 @@ struct GemmArgs {
 };
 
 template <typename T>
-hipError_t launch_project(const cplx<T>* u, cplx<T>* Q, const ProjArgs& a, const T* Wp, hipStream_t s);
+hipError_t launch_project(const cplx<T>* uT, cplx<T>* Q, const ProjArgs& a, const T* Wp, hipStream_t s);
 template <typename T>
 hipError_t launch_convolve(const cplx<T>* Q, cplx<T>* Phi, cplx<T>* S, const ConvArgs& a, hipStream_t s,
                            hipEvent_t* ev = nullptr);
 template <typename T>
-hipError_t launch_combine(int mode, const cplx<T>* Phi, const cplx<T>* u, const cplx<T>* x, cplx<T>* y,
-                          const CombineArgs& a, const T* Wt, const cplx<T>* near_val, const cplx<T>* d_val,
-                          hipStream_t s);
+hipError_t launch_near(const cplx<T>* uT, cplx<T>* nf, const NearArgs& a, const cplx<T>* near_val, hipStream_t s);
+template <typename T>
+hipError_t launch_interp(int mode, const cplx<T>* Phi, const cplx<T>* nf, const cplx<T>* x, cplx<T>* y,
+                         const InterpArgs& a, const T* Wt, const cplx<T>* d_val, hipStream_t s);
+template <typename T>
+hipError_t launch_transpose(const cplx<T>* x, cplx<T>* xT, int R, int ne, int N, hipStream_t s);
 template <typename T>
 hipError_t launch_macro(const cplx<T>* M, const cplx<T>* X, cplx<T>* U, const GemmArgs& a, hipStream_t s);
 hipError_t launch_spectrum(cplx<double>* raw, int Lx, int Ly, int nz, double k, double h, const FftPlan& Px,

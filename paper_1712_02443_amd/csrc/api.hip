@@ -36,6 +36,8 @@ static FftPlan make_plan(int L, std::vector<int>& rev, std::vector<int>& pos) {
     P.radix[s] = f[s];
     P.stride[s] = B / f[s];
     P.tw_step[s] = L / B;
+    P.div_nb[s] = magic_div(unsigned(L / f[s]));
+    P.div_S[s] = magic_div(unsigned(P.stride[s]));
     B = P.stride[s];
   }
   rev.assign(L, 0);
@@ -145,37 +147,57 @@ static ProjArgs proj_args(aim_op* op, int R) {
   a.q3 = st.q3;
   a.node_ptr = op->node_ptr;
   a.node_ent = op->node_ent;
+  a.node_n = op->node_n;
   return a;
 }
 
-static CombineArgs combine_args(aim_op* op, int R) {
+static NearArgs near_args(aim_op* op, int R) {
   const Setup& st = op->st;
-  CombineArgs a{};
+  NearArgs a{};
   a.R = R;
   a.ne = op->ne;
   a.N = st.N;
   a.px = op->arr.px;
+  a.py = op->arr.py;
+  a.offsets = op->offsets_d;
+  a.near_ptr = op->near_ptr;
+  a.near_col = op->near_col;
+  return a;
+}
+
+template <typename T>
+static InterpArgs interp_args(aim_op* op, int R) {
+  const Setup& st = op->st;
+  InterpArgs a{};
+  a.R = R;
+  a.ne = op->ne;
+  a.N = st.N;
+  a.px = op->arr.px;
+  a.py = op->arr.py;
   a.pitch = op->arr.pitch;
   a.nx = st.nx;
   a.ny = st.ny;
   a.nz = st.nz;
   a.q = st.q;
   a.q3 = st.q3;
-  a.n_off = int(st.offsets.size() / 2);
+  a.ex = st.ex;
+  a.ey = st.ey;
   a.keta = op->arr.k * op->arr.eta;
   a.sig_phi = -1.0 / (op->arr.k * op->arr.k);
   a.sloc = op->sloc;
-  a.near_ptr = op->near_ptr;
-  a.near_col = op->near_col;
-  a.nbr = op->nbr;
   a.d_ptr = op->d_ptr;
   a.d_col = op->d_col;
+  // two elements per tile along x when the lattice is wide enough and the box fits
+  a.TX = op->arr.px >= 8 ? 2 : 1;
+  a.TY = 1;
+  if (interp_lds_bytes(a, sizeof(cplx<T>)) > op->lds_max) a.TX = 1;
   return a;
 }
 
 static GemmArgs gemm_args(aim_op* op, int R) {
   GemmArgs a{};
   a.N = op->N;
+  a.ne = op->ne;
   a.R = R;
   a.n_types = op->n_types;
   a.col_list = op->col_list;
@@ -223,26 +245,29 @@ static int check_common(aim_op* op, const void* a, const void* b, int32_t nrhs, 
   return AIM_OK;
 }
 
-// ev (optional): 7 events recorded before the first kernel and after each of the six.
+// ev (optional): 8 events, recorded before the first kernel and after each of the
+// seven (GEMM or transpose, projection, three FFT passes, near field, interpolation).
 template <typename T>
 int matvec_impl(aim_op* op, const cplx<T>* x, cplx<T>* y, int R, int flags, hipStream_t s, hipEvent_t* ev = nullptr) {
   PrecData<T>& P = prec_data<T>(op);
-  cplx<T>* u = static_cast<cplx<T>*>(op->u);
+  cplx<T>* uT = static_cast<cplx<T>*>(op->u);
+  cplx<T>* nf = static_cast<cplx<T>*>(op->nf);
   cplx<T>* grid = static_cast<cplx<T>*>(op->grid);
   cplx<T>* S = static_cast<cplx<T>*>(op->S);
-  const cplx<T>* src = x;
   if (ev) AIM_HIP(hipEventRecord(ev[0], s));
-  if (flags == AIM_FULL) {
-    AIM_HIP(launch_macro<T>(P.M, x, u, gemm_args(op, R), s));
-    src = u;
-  }
+  if (flags == AIM_FULL)
+    AIM_HIP(launch_macro<T>(P.M, x, uT, gemm_args(op, R), s));
+  else
+    AIM_HIP(launch_transpose<T>(x, uT, R, op->ne, op->N, s));
   if (ev) AIM_HIP(hipEventRecord(ev[1], s));
-  AIM_HIP(launch_project<T>(src, grid, proj_args(op, R), P.Wp, s));
+  AIM_HIP(launch_project<T>(uT, grid, proj_args(op, R), P.Wp, s));
   if (ev) AIM_HIP(hipEventRecord(ev[2], s));
   AIM_HIP(launch_convolve<T>(grid, grid, S, conv_args(op, P, R), s, ev ? ev + 3 : nullptr));
   if (ev) AIM_HIP(hipEventRecord(ev[5], s));
-  AIM_HIP(launch_combine<T>(flags, grid, src, x, y, combine_args(op, R), P.Wt, P.near, P.dval, s));
+  if (flags != AIM_FAR_ONLY) AIM_HIP(launch_near<T>(uT, nf, near_args(op, R), P.near, s));
   if (ev) AIM_HIP(hipEventRecord(ev[6], s));
+  AIM_HIP(launch_interp<T>(flags, grid, nf, x, y, interp_args<T>(op, R), P.Wt, P.dval, s));
+  if (ev) AIM_HIP(hipEventRecord(ev[7], s));
   return AIM_OK;
 }
 
@@ -251,20 +276,20 @@ template int matvec_impl<float>(aim_op*, const cplx<float>*, cplx<float>*, int, 
 
 template <typename T>
 static int time_kernels(aim_op* op, const cplx<T>* x, cplx<T>* y, int R, int reps, double* ms, hipStream_t s) {
-  hipEvent_t ev[7];
+  hipEvent_t ev[8];
   for (auto& e : ev) AIM_HIP(hipEventCreate(&e));
-  double acc[6] = {0, 0, 0, 0, 0, 0};
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
   int rc = AIM_OK;
   for (int it = 0; it <= reps && rc == AIM_OK; ++it) {
     rc = matvec_impl<T>(op, x, y, R, AIM_FULL, s, ev);
     if (rc) break;
-    if (hipEventSynchronize(ev[6]) != hipSuccess) {
+    if (hipEventSynchronize(ev[7]) != hipSuccess) {
       set_error("event synchronisation failed");
       rc = AIM_EDEVICE;
       break;
     }
     if (it == 0) continue;  // warm-up
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < 7; ++k) {
       float t = 0;
       (void)hipEventElapsedTime(&t, ev[k], ev[k + 1]);
       acc[k] += t;
@@ -272,7 +297,7 @@ static int time_kernels(aim_op* op, const cplx<T>* x, cplx<T>* y, int R, int rep
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
   if (rc == AIM_OK)
-    for (int k = 0; k < 6; ++k) ms[k] = acc[k] / reps;
+    for (int k = 0; k < 7; ++k) ms[k] = acc[k] / reps;
   return rc;
 }
 
@@ -325,6 +350,7 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
     build_setup(s, a, op->st);
     Setup& st = op->st;
     if (st.nz > kMaxNz) throw std::invalid_argument("grid extent along z exceeds 16 nodes");
+    if (st.offsets.size() / 2 > size_t(kMaxOffsets)) throw std::invalid_argument("too many near-field offsets");
     op->ne = a.px * a.py;
     op->N = st.N;
     op->R_max = a.max_rhs;
@@ -347,6 +373,7 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
     op->sloc = upload(op, st.sloc.data(), st.sloc.size());
     op->node_ptr = upload(op, st.node_ptr.data(), st.node_ptr.size());
     op->node_ent = upload(op, st.node_ent.data(), st.node_ent.size());
+    op->node_n = upload(op, st.node_n.data(), st.node_n.size());
     op->near_ptr = upload(op, st.near_ptr.data(), st.near_ptr.size());
     op->near_col = upload(op, st.near_col.data(), st.near_col.size());
     op->rev_x = upload(op, rx.data(), rx.size());
@@ -361,6 +388,7 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
       }
     }
     op->nbr = upload(op, nbr.data(), nbr.size());
+    op->offsets_d = upload(op, st.offsets.data(), st.offsets.size());
     // macromodel column lists, r-major within each kind
     op->type_count.assign(a.n_types, 0);
     op->col_start.assign(a.n_types, 0);
@@ -402,6 +430,7 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
     // workspaces, sized for complex128
     const size_t n_unk = size_t(op->ne) * op->N * a.max_rhs;
     op->u = op->mem.alloc<cplx<double>>(n_unk);
+    op->nf = op->mem.alloc<cplx<double>>(n_unk);
     op->grid = op->mem.alloc<cplx<double>>(size_t(a.max_rhs) * 4 * st.nx * st.ny * st.nz);
     op->S = op->mem.alloc<cplx<double>>(size_t(a.max_rhs) * 4 * st.nx * op->Ly * st.nz);
   } catch (const std::bad_alloc&) {
@@ -518,12 +547,17 @@ int macro_apply(aim_op* op, const void* x, void* u, int32_t nrhs, int32_t precis
     return AIM_ESTATE;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (precision == AIM_FP64)
-    AIM_HIP(launch_macro<double>(op->p64.M, static_cast<const cplx<double>*>(x), static_cast<cplx<double>*>(u),
-                                 gemm_args(op, nrhs), s));
-  else
-    AIM_HIP(launch_macro<float>(op->p32.M, static_cast<const cplx<float>*>(x), static_cast<cplx<float>*>(u),
-                                gemm_args(op, nrhs), s));
+  // the GEMM writes element-fastest; transposing [N][ne] back is the same kernel with
+  // the two extents swapped
+  if (precision == AIM_FP64) {
+    cplx<double>* uT = static_cast<cplx<double>*>(op->u);
+    AIM_HIP(launch_macro<double>(op->p64.M, static_cast<const cplx<double>*>(x), uT, gemm_args(op, nrhs), s));
+    AIM_HIP(launch_transpose<double>(uT, static_cast<cplx<double>*>(u), nrhs, op->N, op->ne, s));
+  } else {
+    cplx<float>* uT = static_cast<cplx<float>*>(op->u);
+    AIM_HIP(launch_macro<float>(op->p32.M, static_cast<const cplx<float>*>(x), uT, gemm_args(op, nrhs), s));
+    AIM_HIP(launch_transpose<float>(uT, static_cast<cplx<float>*>(u), nrhs, op->N, op->ne, s));
+  }
   return AIM_OK;
 }
 
@@ -571,12 +605,15 @@ int aim_project(aim_op* op, const void* u, void* Q, int32_t nrhs, int32_t precis
   int c = check_common(op, u, Q, nrhs, precision);
   if (c) return c;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (precision == AIM_FP64)
-    AIM_HIP(launch_project<double>(static_cast<const cplx<double>*>(u), static_cast<cplx<double>*>(Q),
-                                   proj_args(op, nrhs), op->p64.Wp, s));
-  else
-    AIM_HIP(launch_project<float>(static_cast<const cplx<float>*>(u), static_cast<cplx<float>*>(Q),
-                                  proj_args(op, nrhs), op->p32.Wp, s));
+  if (precision == AIM_FP64) {
+    cplx<double>* uT = static_cast<cplx<double>*>(op->u);
+    AIM_HIP(launch_transpose<double>(static_cast<const cplx<double>*>(u), uT, nrhs, op->ne, op->N, s));
+    AIM_HIP(launch_project<double>(uT, static_cast<cplx<double>*>(Q), proj_args(op, nrhs), op->p64.Wp, s));
+  } else {
+    cplx<float>* uT = static_cast<cplx<float>*>(op->u);
+    AIM_HIP(launch_transpose<float>(static_cast<const cplx<float>*>(u), uT, nrhs, op->ne, op->N, s));
+    AIM_HIP(launch_project<float>(uT, static_cast<cplx<float>*>(Q), proj_args(op, nrhs), op->p32.Wp, s));
+  }
   return AIM_OK;
 }
 
@@ -677,8 +714,8 @@ int aim_get_near(const aim_op* op, int32_t* rows, int32_t* offs, int32_t* cols, 
   for (int n = 0; n < st.N; ++n)
     for (int e = st.near_ptr[n]; e < st.near_ptr[n + 1]; ++e) {
       rows[e] = n;
-      offs[e] = st.near_col[e] / st.N;
-      cols[e] = st.near_col[e] % st.N;
+      offs[e] = st.near_col[e] >> 16;
+      cols[e] = st.near_col[e] & 0xFFFF;
       vals[2 * e] = st.near_val[e].real();
       vals[2 * e + 1] = st.near_val[e].imag();
     }

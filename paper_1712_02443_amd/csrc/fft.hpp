@@ -11,6 +11,10 @@
 // Inverse transform: the stages undone in reverse order with conjugate twiddles and
 // the inverse DFT; it reads digit-reversed input and returns natural order, scaled
 // by L.  A convolution therefore never needs a permutation pass.
+//
+// Every stage is compiled for its radix (values stay in registers); integer
+// divisions by the per-stage counts use precomputed multipliers: for n d < 2^32,
+// n / d = umulhi(n, floor((2^32 - 1) / d) + 1).
 #pragma once
 
 #include "device_common.hpp"
@@ -23,25 +27,32 @@ struct FftPlan {
   int L;
   int nst;
   int radix[kMaxStages];
-  int stride[kMaxStages];  // S_s
-  int tw_step[kMaxStages]; // L / B_s
+  int stride[kMaxStages];     // S_s
+  int tw_step[kMaxStages];    // L / B_s
+  unsigned div_nb[kMaxStages];  // multiplier for division by L / r_s
+  unsigned div_S[kMaxStages];   // multiplier for division by S_s
 };
 
-template <typename T>
-__device__ __forceinline__ void dft_small(cplx<T>* x, int r, T sgn) {
-  // sgn = +1: forward (exp(-2 pi i / r)), sgn = -1: inverse.
-  if (r == 2) {
+__host__ __device__ inline unsigned magic_div(unsigned d) { return d == 1 ? 0u : 0xFFFFFFFFu / d + 1u; }
+__device__ __forceinline__ int fast_div(int n, unsigned magic) {
+  return magic == 0u ? n : int(__umulhi(unsigned(n), magic));
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dft_r(cplx<T>* x, T sgn) {
+  // sgn = +1: forward (exp(-2 pi i / R)), sgn = -1: inverse.
+  if constexpr (R == 2) {
     cplx<T> a = x[0], b = x[1];
     x[0] = cadd(a, b);
     x[1] = csub(a, b);
-  } else if (r == 4) {
+  } else if constexpr (R == 4) {
     cplx<T> a0 = cadd(x[0], x[2]), a1 = csub(x[0], x[2]);
     cplx<T> b0 = cadd(x[1], x[3]), b1 = cmul_mi(csub(x[1], x[3]), sgn);
     x[0] = cadd(a0, b0);
     x[2] = csub(a0, b0);
     x[1] = cadd(a1, b1);
     x[3] = csub(a1, b1);
-  } else if (r == 3) {
+  } else if constexpr (R == 3) {
     const T s3 = T(0.86602540378443864676);
     cplx<T> t1 = cadd(x[1], x[2]);
     cplx<T> t2 = cscale(cmul_mi(csub(x[1], x[2]), sgn), s3);
@@ -49,7 +60,8 @@ __device__ __forceinline__ void dft_small(cplx<T>* x, int r, T sgn) {
     x[0] = cadd(x[0], t1);
     x[1] = cadd(m, t2);
     x[2] = csub(m, t2);
-  } else {  // 5
+  } else {
+    static_assert(R == 5, "radix");
     const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);
     const T s1 = T(0.95105651629515357212), s2 = T(0.58778525229247312917);
     cplx<T> a1 = cadd(x[1], x[4]), b1 = csub(x[1], x[4]);
@@ -67,25 +79,55 @@ __device__ __forceinline__ void dft_small(cplx<T>* x, int r, T sgn) {
   }
 }
 
+template <typename T, int R, bool FWD>
+__device__ __forceinline__ void fft_stage(cplx<T>* buf, int ld, int nlines, const FftPlan& P, int s,
+                                          const cplx<T>* tw) {
+  const int S = P.stride[s], step = P.tw_step[s];
+  const unsigned mnb = P.div_nb[s], mS = P.div_S[s];
+  const int nb = P.L / R;
+  const int items = nb * nlines;
+  for (int it = threadIdx.x; it < items; it += blockDim.x) {
+    const int line = fast_div(it, mnb);
+    const int t = it - line * nb;
+    const int blk = fast_div(t, mS);
+    const int j = t - blk * S;
+    cplx<T>* base = buf + line * ld + blk * S * R + j;
+    cplx<T> x[R];
+    if constexpr (FWD) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) x[i] = base[i * S];
+      dft_r<T, R>(x, T(1));
+      base[0] = x[0];
+#pragma unroll
+      for (int qo = 1; qo < R; ++qo) base[qo * S] = cmul(x[qo], tw[j * qo * step]);
+    } else {
+      x[0] = base[0];
+#pragma unroll
+      for (int qo = 1; qo < R; ++qo) x[qo] = cmulc(base[qo * S], tw[j * qo * step]);
+      dft_r<T, R>(x, T(-1));
+#pragma unroll
+      for (int i = 0; i < R; ++i) base[i * S] = x[i];
+    }
+  }
+}
+
+template <typename T, bool FWD>
+__device__ __forceinline__ void fft_stage_any(cplx<T>* buf, int ld, int nlines, const FftPlan& P, int s,
+                                              const cplx<T>* tw) {
+  switch (P.radix[s]) {
+    case 2: fft_stage<T, 2, FWD>(buf, ld, nlines, P, s, tw); break;
+    case 3: fft_stage<T, 3, FWD>(buf, ld, nlines, P, s, tw); break;
+    case 4: fft_stage<T, 4, FWD>(buf, ld, nlines, P, s, tw); break;
+    default: fft_stage<T, 5, FWD>(buf, ld, nlines, P, s, tw); break;
+  }
+}
+
 // Forward (DIF) transform of nlines lines at buf + line * ld, in place.
 // tw[t] = exp(-2 pi i t / L).  Ends with a barrier.
 template <typename T>
 __device__ void lds_fft_fwd(cplx<T>* buf, int ld, int nlines, const FftPlan& P, const cplx<T>* tw) {
-  const int L = P.L;
   for (int s = 0; s < P.nst; ++s) {
-    const int r = P.radix[s], S = P.stride[s], step = P.tw_step[s];
-    const int nb = L / r;
-    const int items = nb * nlines;
-    for (int it = threadIdx.x; it < items; it += blockDim.x) {
-      const int line = it / nb, t = it - line * nb;
-      const int blk = t / S, j = t - blk * S;
-      cplx<T>* base = buf + line * ld + blk * S * r + j;
-      cplx<T> x[5];
-      for (int i = 0; i < r; ++i) x[i] = base[i * S];
-      dft_small(x, r, T(1));
-      base[0] = x[0];
-      for (int qo = 1; qo < r; ++qo) base[qo * S] = cmul(x[qo], tw[j * qo * step]);
-    }
+    fft_stage_any<T, true>(buf, ld, nlines, P, s, tw);
     __syncthreads();
   }
 }
@@ -93,21 +135,8 @@ __device__ void lds_fft_fwd(cplx<T>* buf, int ld, int nlines, const FftPlan& P, 
 // Inverse (DIT) transform, digit-reversed in, natural out, scaled by L.
 template <typename T>
 __device__ void lds_fft_inv(cplx<T>* buf, int ld, int nlines, const FftPlan& P, const cplx<T>* tw) {
-  const int L = P.L;
   for (int s = P.nst - 1; s >= 0; --s) {
-    const int r = P.radix[s], S = P.stride[s], step = P.tw_step[s];
-    const int nb = L / r;
-    const int items = nb * nlines;
-    for (int it = threadIdx.x; it < items; it += blockDim.x) {
-      const int line = it / nb, t = it - line * nb;
-      const int blk = t / S, j = t - blk * S;
-      cplx<T>* base = buf + line * ld + blk * S * r + j;
-      cplx<T> x[5];
-      x[0] = base[0];
-      for (int qo = 1; qo < r; ++qo) x[qo] = cmulc(base[qo * S], tw[j * qo * step]);
-      dft_small(x, r, T(-1));
-      for (int i = 0; i < r; ++i) base[i * S] = x[i];
-    }
+    fft_stage_any<T, false>(buf, ld, nlines, P, s, tw);
     __syncthreads();
   }
 }

@@ -25,7 +25,7 @@ int matvec_impl(aim_op* op, const cplx<T>* x, cplx<T>* y, int R, int flags, hipS
 namespace {
 
 constexpr int kBS = 256;
-constexpr int kE = 8;
+constexpr int kE = 4;
 constexpr int kChunk = kBS * kE;
 
 template <typename T>
@@ -59,12 +59,14 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
   }
 }
 
-// part[(r * nv + i) * nch + c] = sum over chunk c of conj(V_i[r]) . w[r], i < nv
+// part[((r * nv + i) * nch + c) * 2 + {0,1}] = sum over chunk c of conj(V_i[r]) . w[r], i < nv.
+// Each wave reduces its own partial per i with lane shuffles; one barrier at the end.
 template <typename Tb>
 __global__ void __launch_bounds__(kBS) k_dots(const cplx<Tb>* __restrict__ V, const cplx<double>* __restrict__ w,
                                               double* __restrict__ part, int64_t n, int nv, int R) {
-  __shared__ double sh[2 * kBS / 64];
+  extern __shared__ double wsum[];  // [nv][4 waves][2]
   const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t base = int64_t(c) * kChunk;
   cplx<double> wl[kE];
 #pragma unroll
@@ -78,39 +80,52 @@ __global__ void __launch_bounds__(kBS) k_dots(const cplx<Tb>* __restrict__ V, co
 #pragma unroll
     for (int e = 0; e < kE; ++e) {
       const int64_t k = base + e * kBS + threadIdx.x;
-      if (k < n) {
-        const cplx<double> v = up(vi[k]);
-        a += v.re * wl[e].re + v.im * wl[e].im;
-        b += v.re * wl[e].im - v.im * wl[e].re;
-      }
+      const cplx<double> v = k < n ? up(vi[k]) : cmk<double>(0, 0);
+      a += v.re * wl[e].re + v.im * wl[e].im;
+      b += v.re * wl[e].im - v.im * wl[e].re;
     }
-    block_sum2(a, b, sh);
-    if (threadIdx.x == 0) {
-      part[(int64_t(r) * nv + i) * nch * 2 + 2 * c] = a;
-      part[(int64_t(r) * nv + i) * nch * 2 + 2 * c + 1] = b;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) {
+      wsum[(i * 4 + wave) * 2] = a;
+      wsum[(i * 4 + wave) * 2 + 1] = b;
     }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+    double a = 0, b = 0;
+    for (int q = 0; q < 4; ++q) {
+      a += wsum[(i * 4 + q) * 2];
+      b += wsum[(i * 4 + q) * 2 + 1];
+    }
+    part[((int64_t(r) * nv + i) * nch + c) * 2] = a;
+    part[((int64_t(r) * nv + i) * nch + c) * 2 + 1] = b;
   }
 }
 
-// h[r][i] (+)= sum_c part ; one thread per (r, i)
-__global__ void k_reduce_dots(const double* __restrict__ part, cplx<double>* h, int nch, int nv, int R, int ldh,
-                              int accumulate) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// h[r][i] (+)= sum_c part ; one wave per (r, i), fixed summation order
+__global__ void __launch_bounds__(64) k_reduce_dots(const double* __restrict__ part, cplx<double>* h, int nch, int nv,
+                                                    int R, int ldh, int accumulate) {
+  const int t = blockIdx.x;
   if (t >= nv * R) return;
   const int r = t / nv, i = t - r * nv;
   const double* p = part + int64_t(t) * nch * 2;
   double a = 0, b = 0;
-  for (int c = 0; c < nch; ++c) {
+  for (int c = threadIdx.x; c < nch; c += 64) {
     a += p[2 * c];
     b += p[2 * c + 1];
   }
-  cplx<double>& o = h[int64_t(r) * ldh + i];
-  if (accumulate) {
-    o.re += a;
-    o.im += b;
-  } else {
-    o.re = a;
-    o.im = b;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (threadIdx.x == 0) {
+    cplx<double>& o = h[int64_t(r) * ldh + i];
+    if (accumulate) {
+      o.re += a;
+      o.im += b;
+    } else {
+      o.re = a;
+      o.im = b;
+    }
   }
 }
 
@@ -123,20 +138,31 @@ __global__ void __launch_bounds__(kBS) k_update(const cplx<Tb>* __restrict__ V, 
   const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
   const int64_t base = int64_t(c) * kChunk;
   const cplx<double>* cf = coef + int64_t(r) * ldc;
+  cplx<double> acc[kE];
+#pragma unroll
+  for (int e = 0; e < kE; ++e) {
+    const int64_t k = base + e * kBS + threadIdx.x;
+    acc[e] = k < n ? w[int64_t(r) * n + k] : cmk<double>(0, 0);
+  }
+  for (int i = 0; i < nv; ++i) {
+    const cplx<double> h = cf[i];
+    const cplx<Tb>* vi = V + (int64_t(i) * R + r) * n;
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+      const int64_t k = base + e * kBS + threadIdx.x;
+      const cplx<double> v = k < n ? up(vi[k]) : cmk<double>(0, 0);
+      acc[e].re -= v.re * h.re - v.im * h.im;
+      acc[e].im -= v.re * h.im + v.im * h.re;
+    }
+  }
   double nn = 0, dummy = 0;
 #pragma unroll
   for (int e = 0; e < kE; ++e) {
     const int64_t k = base + e * kBS + threadIdx.x;
-    if (k >= n) continue;
-    cplx<double> acc = w[int64_t(r) * n + k];
-    for (int i = 0; i < nv; ++i) {
-      const cplx<double> v = up(V[(int64_t(i) * R + r) * n + k]);
-      const cplx<double> h = cf[i];
-      acc.re -= v.re * h.re - v.im * h.im;
-      acc.im -= v.re * h.im + v.im * h.re;
+    if (k < n) {
+      w[int64_t(r) * n + k] = acc[e];
+      nn += acc[e].re * acc[e].re + acc[e].im * acc[e].im;
     }
-    w[int64_t(r) * n + k] = acc;
-    nn += acc.re * acc.re + acc.im * acc.im;
   }
   if (with_norm) {
     block_sum2(nn, dummy, sh);
@@ -165,13 +191,15 @@ __global__ void __launch_bounds__(kBS) k_residual(const cplx<double>* __restrict
   if (threadIdx.x == 0) part[int64_t(r) * nch + c] = nn;
 }
 
-// out[r] = sqrt(sum_c part[r][c])
-__global__ void k_finish_norm(const double* part, double* out, int nch, int R, int stride) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+// out[r] = sqrt(sum_c part[r][c]); one wave per r, fixed summation order
+__global__ void __launch_bounds__(64) k_finish_norm(const double* part, double* out, int nch, int R, int stride) {
+  const int r = blockIdx.x;
   if (r >= R) return;
-  double s = 0;
-  for (int c = 0; c < nch; ++c) s += part[int64_t(r) * nch + c];
-  out[r * stride] = sqrt(s);
+  double s = 0, dummy = 0;
+  for (int c = threadIdx.x; c < nch; c += 64) s += part[int64_t(r) * nch + c];
+  s = wave_sum(s);
+  (void)dummy;
+  if (threadIdx.x == 0) out[r * stride] = sqrt(s);
 }
 
 // v[r] = w[r] / nrm[r] (zero if nrm = 0), stored in the basis precision
@@ -233,23 +261,39 @@ __global__ void k_givens(cplx<double>* H, cplx<double>* cs, cplx<double>* sn, cp
 }
 
 // y = H^-1 g on the leading k columns (back substitution); k = jused[r] if set,
-// j_end if still running, 0 for finished right-hand sides.
-__global__ void k_lsq(const cplx<double>* H, const cplx<double>* g, cplx<double>* y, const int* jused, int m, int R,
-                      int j_end) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+// j_end if still running, 0 for finished right-hand sides.  One wave per right-hand
+// side; the triangle is staged in LDS and each step's sum is a lane reduction.
+__global__ void __launch_bounds__(64) k_lsq(const cplx<double>* H, const cplx<double>* g, cplx<double>* y,
+                                            const int* jused, int m, int R, int j_end) {
+  extern __shared__ cplx<double> Hs[];  // [m][m+1] column-major, then y[m+1]
+  const int r = blockIdx.x;
   if (r >= R) return;
   const int k = jused[r] > 0 ? jused[r] : (jused[r] == 0 ? j_end : 0);
   const cplx<double>* Hr = H + int64_t(r) * m * (m + 1);
-  cplx<double>* yr = y + int64_t(r) * (m + 1);
-  for (int i = k; i <= m; ++i) yr[i] = cmk<double>(0, 0);
+  cplx<double>* ys = Hs + m * (m + 1);
+  for (int t = threadIdx.x; t < k * (m + 1); t += 64) Hs[t] = Hr[t];
+  for (int t = threadIdx.x; t <= m; t += 64) ys[t] = cmk<double>(0, 0);
+  __syncthreads();
   for (int i = k - 1; i >= 0; --i) {
-    cplx<double> acc = g[int64_t(r) * (m + 1) + i];
-    for (int l = i + 1; l < k; ++l) acc = csub(acc, cmul(Hr[int64_t(l) * (m + 1) + i], yr[l]));
-    const cplx<double> d = Hr[int64_t(i) * (m + 1) + i];
-    const double dd = d.re * d.re + d.im * d.im;
-    yr[i] = dd > 0 ? cmk<double>((acc.re * d.re + acc.im * d.im) / dd, (acc.im * d.re - acc.re * d.im) / dd)
-                   : cmk<double>(0, 0);
+    double a = 0, b = 0;
+    for (int l = i + 1 + threadIdx.x; l < k; l += 64) {
+      const cplx<double> p = cmul(Hs[l * (m + 1) + i], ys[l]);
+      a += p.re;
+      b += p.im;
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (threadIdx.x == 0) {
+      const cplx<double> gi = g[int64_t(r) * (m + 1) + i];
+      const cplx<double> acc = cmk<double>(gi.re - a, gi.im - b);
+      const cplx<double> d = Hs[i * (m + 1) + i];
+      const double dd = d.re * d.re + d.im * d.im;
+      ys[i] = dd > 0 ? cmk<double>((acc.re * d.re + acc.im * d.im) / dd, (acc.im * d.re - acc.re * d.im) / dd)
+                     : cmk<double>(0, 0);
+    }
+    __syncthreads();
   }
+  for (int t = threadIdx.x; t <= m; t += 64) y[int64_t(r) * (m + 1) + t] = ys[t];
 }
 
 // x[r] += sum_i V_i[r] y[r][i]  (y is zero beyond the used columns)
@@ -293,7 +337,7 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
   const dim3 gch(nch, R), bs(kBS), g64(nblk(R, 64)), b64(64);
   cplx<Tb>* V = static_cast<cplx<Tb>*>(K.V);
   GM_LAUNCH(k_residual, gch, bs, 0, s, b, (const cplx<double>*)nullptr, (cplx<double>*)nullptr, K.part, n);
-  GM_LAUNCH(k_finish_norm, g64, b64, 0, s, K.part, K.scal + 3, nch, R, 4);
+  GM_LAUNCH(k_finish_norm, dim3(R), b64, 0, s, K.part, K.scal + 3, nch, R, 4);
   if (!o.x0_given) GM_HIP(hipMemsetAsync(x, 0, sizeof(cplx<double>) * n * R, s));
   std::vector<double> bnorm(R), relres(R, 1.0), hs(4 * R);
   std::vector<int> active(R, 1), iters(R, 0), restarts(R, 0), matvecs(R, 0), jused(R), jinit(R);
@@ -307,7 +351,7 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
     int rc = matvec_impl<double>(op, x, K.w, R, AIM_FULL, s);
     if (rc) return rc;
     GM_LAUNCH(k_residual, gch, bs, 0, s, b, K.w, K.r, K.part, n);
-    GM_LAUNCH(k_finish_norm, g64, b64, 0, s, K.part, K.scal, nch, R, 4);
+    GM_LAUNCH(k_finish_norm, dim3(R), b64, 0, s, K.part, K.scal, nch, R, 4);
     GM_HIP(hipMemcpyAsync(hs.data(), K.scal, sizeof(double) * 4 * R, hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
     bool any = false;
@@ -349,13 +393,14 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
       }
       const int nv = j + 1;
       // classical Gram-Schmidt, twice
-      GM_LAUNCH(k_dots<Tb>, gch, bs, 0, s, V, K.w, K.part, n, nv, R);
-      GM_LAUNCH(k_reduce_dots, dim3(nblk(nv * R, 64)), b64, 0, s, K.part, K.hcol, nch, nv, R, m + 1, 0);
+      const size_t dots_lds = sizeof(double) * 8 * nv;
+      GM_LAUNCH(k_dots<Tb>, gch, bs, dots_lds, s, V, K.w, K.part, n, nv, R);
+      GM_LAUNCH(k_reduce_dots, dim3(nv * R), b64, 0, s, K.part, K.hcol, nch, nv, R, m + 1, 0);
       GM_LAUNCH(k_update<Tb>, gch, bs, 0, s, V, K.w, K.hcol, m + 1, K.part, n, nv, R, 0);
-      GM_LAUNCH(k_dots<Tb>, gch, bs, 0, s, V, K.w, K.part, n, nv, R);
-      GM_LAUNCH(k_reduce_dots, dim3(nblk(nv * R, 64)), b64, 0, s, K.part, K.h2, nch, nv, R, m + 1, 0);
+      GM_LAUNCH(k_dots<Tb>, gch, bs, dots_lds, s, V, K.w, K.part, n, nv, R);
+      GM_LAUNCH(k_reduce_dots, dim3(nv * R), b64, 0, s, K.part, K.h2, nch, nv, R, m + 1, 0);
       GM_LAUNCH(k_update<Tb>, gch, bs, 0, s, V, K.w, K.h2, m + 1, K.part, n, nv, R, 1);
-      GM_LAUNCH(k_finish_norm, g64, b64, 0, s, K.part, K.scal, nch, R, 4);
+      GM_LAUNCH(k_finish_norm, dim3(R), b64, 0, s, K.part, K.scal, nch, R, 4);
       GM_LAUNCH(k_scale<Tb>, dim3(nblk(n * R, 256)), dim3(256), 0, s, K.w, V + int64_t(j + 1) * R * n, K.scal, 4, n,
                 R);
       GM_LAUNCH(k_givens, g64, b64, 0, s, K.H, K.cs, K.sn, K.g, K.hcol, K.h2, K.scal, K.active, m, j, R);
@@ -369,7 +414,8 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
         if (all) break;
       }
     }
-    GM_LAUNCH(k_lsq, g64, b64, 0, s, K.H, K.g, K.h2, K.active, m, R, j_end);
+    GM_LAUNCH(k_lsq, dim3(R), b64, sizeof(cplx<double>) * (size_t(m) * (m + 1) + m + 1), s, K.H, K.g, K.h2,
+              K.active, m, R, j_end);
     GM_LAUNCH(k_update_x<Tb>, dim3(nblk(n * R, 256)), dim3(256), 0, s, V, x, K.h2, n, j_end, R, m);
     GM_HIP(hipMemcpyAsync(jused.data(), K.active, sizeof(int) * R, hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
@@ -436,6 +482,8 @@ int ensure_krylov(aim_op* op, int R, int m, int prec) {
   K.R = R;
   K.restart = m;
   K.prec = prec;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_lsq), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            int(sizeof(cplx<double>) * (size_t(m) * (m + 1) + m + 1)));
   return AIM_OK;
 }
 
@@ -454,9 +502,9 @@ extern "C" int gmres_solve(aim_op* op, const void* b, void* x, int32_t nrhs, con
     set_error("gmres: nrhs must be in [1, max_rhs]");
     return AIM_EINVAL;
   }
-  if (opts->restart < 1 || opts->restart > 1000 || opts->max_iters < 0 || !(opts->tol > 0) ||
+  if (opts->restart < 1 || opts->restart > 96 || opts->max_iters < 0 || !(opts->tol > 0) ||
       (opts->precision != AIM_FP64 && opts->precision != AIM_MIXED)) {
-    set_error("gmres: bad options (restart in [1,1000], max_iters >= 0, tol > 0, precision)");
+    set_error("gmres: bad options (restart in [1,96], max_iters >= 0, tol > 0, precision)");
     return AIM_EINVAL;
   }
   if (b == x) {

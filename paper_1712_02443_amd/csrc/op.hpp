@@ -96,11 +96,14 @@ struct aim_op {
   int64_t d_nnz = 0;
   size_t lds_max = 65536;
   aimm::DeviceMem mem;
-  int *sloc = nullptr, *node_ptr = nullptr, *node_ent = nullptr, *near_ptr = nullptr, *near_col = nullptr;
+  int *sloc = nullptr, *node_ptr = nullptr, *node_ent = nullptr, *node_n = nullptr, *near_ptr = nullptr,
+      *near_col = nullptr;
+  int* offsets_d = nullptr;  // [n_off][2] lattice offsets of the near-field blocks
   int *nbr = nullptr, *d_ptr = nullptr, *d_col = nullptr, *rev_x = nullptr, *rev_y = nullptr, *col_list = nullptr;
   aimm::PrecData<double> p64;
   aimm::PrecData<float> p32;
-  void* u = nullptr;      // [R][n] macromodel output (sized for complex128)
+  void* u = nullptr;      // [R][N][n_elem] macromodel output, element-fastest (sized for complex128)
+  void* nf = nullptr;     // [R][n_elem][N] near-field product (sized for complex128)
   void* grid = nullptr;   // Q / Phi (sized for complex128)
   void* S = nullptr;      // spectrum pass buffer (sized for complex128)
   aimm::KrylovWork kw;

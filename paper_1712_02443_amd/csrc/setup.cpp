@@ -278,6 +278,7 @@ void validate(const SurfaceIn& s, const ArrayIn& a) {
   auto bad = [](const std::string& m) { throw std::invalid_argument(m); };
   if (!s.vert || !s.tri || !s.rwg) bad("surface arrays must not be NULL");
   if (s.n_vert < 3 || s.n_tri < 2 || s.n_rwg < 1) bad("surface needs >= 3 vertices, >= 2 triangles, >= 1 RWG");
+  if (s.n_rwg > 65535) bad("at most 65535 RWG functions per surface");
   for (int t = 0; t < 3 * s.n_tri; ++t)
     if (s.tri[t] < 0 || s.tri[t] >= s.n_vert) bad("triangle vertex index out of range");
   for (int n = 0; n < s.n_rwg; ++n) {
@@ -373,9 +374,14 @@ void build_setup(const SurfaceIn& s, const ArrayIn& a, Setup& out) {
   out.node_ptr.assign(nloc + 1, 0);
   for (int i = 0; i < nloc; ++i) out.node_ptr[i + 1] = out.node_ptr[i] + cnt[i + 1];
   out.node_ent.assign(size_t(N) * q3, 0);
+  out.node_n.assign(size_t(N) * q3, 0);
   std::vector<int> fill(out.node_ptr.begin(), out.node_ptr.end() - 1);
   for (int n = 0; n < N; ++n)
-    for (int p = 0; p < q3; ++p) out.node_ent[fill[node_of(n, p)]++] = n * q3 + p;
+    for (int p = 0; p < q3; ++p) {
+      const int at = fill[node_of(n, p)]++;
+      out.node_ent[at] = n * q3 + p;
+      out.node_n[at] = n;
+    }
 
   // grid Green's function on the separations near pairs can reach
   const double k = a.k, eta = a.eta, h = a.h;
@@ -484,7 +490,7 @@ void build_setup(const SurfaceIn& s, const ArrayIn& a, Setup& out) {
     for (size_t oi = 0; oi < offs.size(); ++oi) {
       if (remap[oi] < 0) continue;
       for (const Ent& e : per_off[oi][n]) {
-        out.near_col.push_back(remap[oi] * N + e.col);
+        out.near_col.push_back((remap[oi] << 16) | e.col);
         out.near_val.push_back(e.v);
       }
     }

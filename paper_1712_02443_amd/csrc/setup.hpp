@@ -36,10 +36,11 @@ struct Setup {
   std::vector<double> W;             // [4][N][q3] projection weights, psi = x, y, z, phi
   std::vector<int32_t> offsets;      // [n_off][2] lattice offsets (dx, dy) carrying near pairs
   std::vector<int32_t> near_ptr;     // [N + 1] CSR rows of the pre-corrected near field
-  std::vector<int32_t> near_col;     // packed o * N + n'
+  std::vector<int32_t> near_col;     // packed (o << 16) | n'
   std::vector<cd> near_val;          // pre-corrected values C = G_exact - G_grid
   std::vector<int32_t> node_ptr;     // [ex*ey*ez + 1] projection gather table by local node
   std::vector<int32_t> node_ent;     // packed n * q3 + p
+  std::vector<int32_t> node_n;       // n of the same entries
   std::vector<double> cent;          // [N][3] RWG edge midpoints (element-local)
 };
 

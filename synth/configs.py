@@ -63,7 +63,7 @@ class Workload:
     r_near: float = 0.3
     pitch_cells: int = 6
     seed: int = 0
-    macro_scale: float = 2.0e-3
+    macro_scale: float = 1.0e-3
     _mesh: SurfaceMesh | None = field(default=None, repr=False)
 
     @property
