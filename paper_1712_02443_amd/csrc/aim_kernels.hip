@@ -10,6 +10,10 @@
 
 namespace aimm {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 // ---- step (i): projection, owner-computes gather --------------------------------
 // Grid node g is written by exactly one element (its owner: the element whose
 // pitch-wide home cell contains g, the last row/column owning the tail).  The owner
@@ -251,6 +255,74 @@ __global__ void __launch_bounds__(256) k_near(const cplx<T>* __restrict__ uT, cp
   }
 }
 
+// ---- pre-corrected near field on the matrix cores ---------------------------------
+// Rows are taken in groups of kNearGroup (16); a group's coefficients form a dense
+// 16 x K block over the union of its columns (o, n').  One wave computes 16 rows x 16
+// elements: A (16 x 4) straight from the block, B (4 x 16) = u of the 16 elements'
+// neighbours at offset o, column n' (element-fastest, so each k reads 16 consecutive
+// values).  Four real MFMAs per complex step.
+template <typename T>
+struct NearMfma;
+template <>
+struct NearMfma<float> {
+  typedef f32x4 acc_t;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct NearMfma<double> {
+  typedef f64x4 acc_t;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+// output row of register r in lane l: v_mfma_f32_16x16x4f32 keeps four consecutive
+// rows per lane group, v_mfma_f64_16x16x4f64 interleaves them (measured on gfx950)
+template <typename T>
+__device__ __forceinline__ int mfma16_row(int lane, int r) {
+  return sizeof(T) == 4 ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_near_mfma(const cplx<T>* __restrict__ uT, cplx<T>* __restrict__ nf,
+                                                   NearArgs a, const int* __restrict__ grp_ptr,
+                                                   const int* __restrict__ grp_col,
+                                                   const cplx<T>* __restrict__ grp_A) {
+  using M = NearMfma<T>;
+  __shared__ cplx<T> tile[kNearGroupDev][65];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int mblk = blockIdx.x * 64, g = blockIdx.y, r = blockIdx.z;
+  const int jcol = lane & 15, kq = lane >> 4;
+  const int mb = mblk + wave * 16 + jcol;
+  const bool validb = mb < a.ne;
+  const int ix = mb % a.px, iy = mb / a.px;
+  const cplx<T>* ur = uT + int64_t(r) * a.N * a.ne;
+  typename M::acc_t accR = {}, accI = {};
+  const int k0 = grp_ptr[g], k1 = grp_ptr[g + 1];
+#pragma unroll 2
+  for (int k = k0; k < k1; k += 4) {
+    const int col = grp_col[k + kq];
+    const int o = col >> 16, np_ = col & 0xFFFF;
+    const int jx = ix + a.offsets[2 * o], jy = iy + a.offsets[2 * o + 1];
+    const bool ok = validb && jx >= 0 && jx < a.px && jy >= 0 && jy < a.py;
+    const cplx<T> bv = ok ? ur[int64_t(np_) * a.ne + jy * a.px + jx] : cmk<T>(0, 0);
+    const cplx<T> av = grp_A[int64_t(k + kq) * kNearGroupDev + jcol];
+    accR = M::mma(av.re, bv.re, accR);
+    accR = M::mma(-av.im, bv.im, accR);
+    accI = M::mma(av.re, bv.im, accI);
+    accI = M::mma(av.im, bv.re, accI);
+  }
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) tile[mfma16_row<T>(lane, rr)][wave * 16 + jcol] = cmk<T>(accR[rr], accI[rr]);
+  __syncthreads();
+  const int n0 = g * kNearGroupDev;
+  for (int idx = threadIdx.x; idx < 64 * kNearGroupDev; idx += 256) {
+    const int mm = idx / kNearGroupDev, nn = idx - mm * kNearGroupDev;
+    if (mblk + mm < a.ne && n0 + nn < a.N) nf[(int64_t(r) * a.ne + mblk + mm) * a.N + n0 + nn] = tile[nn][mm];
+  }
+}
+
 // ---- step (iii) + combine: one workgroup per tile of elements ---------------------
 // The tile's box of grid potentials (4 psi) is staged in LDS; every basis gathers its
 // (N_O+1)^3 nodes per psi from LDS.  MODE 0: y = D x - (v + nf); 1: y = v + nf;
@@ -326,8 +398,6 @@ __global__ void __launch_bounds__(256) k_interp(const cplx<T>* __restrict__ Phi,
 // on the matrix cores: each complex step is four real MFMAs (re*re - im*im,
 // re*im + im*re).  A 64 x 64 output tile per workgroup (2 x 2 waves); M_t and X
 // tiles are staged in LDS; the output is written element-fastest, uT[r][i][m].
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
 __device__ __forceinline__ void gemm_tile_setup(const GemmArgs& a, int& t, int& c0, int* cols, int64_t* colbase) {
@@ -581,8 +651,16 @@ hipError_t launch_convolve(const cplx<T>* Q, cplx<T>* Phi, cplx<T>* S, const Con
 
 template <typename T>
 hipError_t launch_near(const cplx<T>* uT, cplx<T>* nf, const NearArgs& a, const cplx<T>* near_val, hipStream_t s) {
-  const dim3 g((a.N + kNearRows - 1) / kNearRows, (a.ne + 63) / 64, a.R);
-  hipLaunchKernelGGL(k_near<T>, g, dim3(256), 0, s, uT, nf, a, near_val);
+  if (a.grp_A) {
+    // element blocks fastest, so consecutive workgroups (spread over the XCDs) share
+    // the rows of u they read
+    const dim3 g((a.ne + 63) / 64, (a.N + kNearGroupDev - 1) / kNearGroupDev, a.R);
+    hipLaunchKernelGGL(k_near_mfma<T>, g, dim3(256), 0, s, uT, nf, a, a.grp_ptr, a.grp_col,
+                       reinterpret_cast<const cplx<T>*>(a.grp_A));
+  } else {
+    const dim3 g((a.N + kNearRows - 1) / kNearRows, (a.ne + 63) / 64, a.R);
+    hipLaunchKernelGGL(k_near<T>, g, dim3(256), 0, s, uT, nf, a, near_val);
+  }
   return hipGetLastError();
 }
 

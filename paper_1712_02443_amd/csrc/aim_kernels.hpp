@@ -32,11 +32,16 @@ struct ConvArgs {
   const int* rev_y;
 };
 
+constexpr int kNearGroupDev = 16;  // rows per matrix-core near-field group
+
 struct NearArgs {
   int R, ne, N, px, py;
   const int* offsets;  // [n_off][2] (dx, dy)
   const int* near_ptr;
   const int* near_col;
+  const int* grp_ptr;  // row-group tables (matrix-core path); grp_A == nullptr selects the CSR path
+  const int* grp_col;
+  const void* grp_A;
 };
 
 struct InterpArgs {

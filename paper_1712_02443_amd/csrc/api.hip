@@ -1,6 +1,7 @@
 // C ABI of the library: operator construction, the final-system product of
 // eq. MV_product1 and its parts.  GMRES lives in gmres.hip.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <stdexcept>
 #include <string>
@@ -94,6 +95,12 @@ static void fill_prec(aim_op* op, PrecData<T>& P) {
     nv[i].im = T(st.near_val[i].imag());
   }
   P.near = upload(op, nv.data(), nv.size());
+  std::vector<cplx<T>> ga(st.grp_A.size());
+  for (size_t i = 0; i < ga.size(); ++i) {
+    ga[i].re = T(st.grp_A[i].real());
+    ga[i].im = T(st.grp_A[i].imag());
+  }
+  P.grpA = upload(op, ga.data(), ga.size());
   std::vector<cplx<T>> tw;
   twiddles<T>(op->Lx, tw);
   P.tw_x = upload(op, tw.data(), tw.size());
@@ -160,6 +167,9 @@ static NearArgs near_args(aim_op* op, int R) {
   a.px = op->arr.px;
   a.py = op->arr.py;
   a.offsets = op->offsets_d;
+  a.grp_ptr = op->grp_ptr;
+  a.grp_col = op->grp_col;
+  a.grp_A = nullptr;
   a.near_ptr = op->near_ptr;
   a.near_col = op->near_col;
   return a;
@@ -264,7 +274,11 @@ int matvec_impl(aim_op* op, const cplx<T>* x, cplx<T>* y, int R, int flags, hipS
   if (ev) AIM_HIP(hipEventRecord(ev[2], s));
   AIM_HIP(launch_convolve<T>(grid, grid, S, conv_args(op, P, R), s, ev ? ev + 3 : nullptr));
   if (ev) AIM_HIP(hipEventRecord(ev[5], s));
-  if (flags != AIM_FAR_ONLY) AIM_HIP(launch_near<T>(uT, nf, near_args(op, R), P.near, s));
+  if (flags != AIM_FAR_ONLY) {
+    NearArgs na = near_args(op, R);
+    if (op->near_mfma) na.grp_A = P.grpA;
+    AIM_HIP(launch_near<T>(uT, nf, na, P.near, s));
+  }
   if (ev) AIM_HIP(hipEventRecord(ev[6], s));
   AIM_HIP(launch_interp<T>(flags, grid, nf, x, y, interp_args<T>(op, R), P.Wt, P.dval, s));
   if (ev) AIM_HIP(hipEventRecord(ev[7], s));
@@ -389,6 +403,9 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
     }
     op->nbr = upload(op, nbr.data(), nbr.size());
     op->offsets_d = upload(op, st.offsets.data(), st.offsets.size());
+    op->grp_ptr = upload(op, st.grp_ptr.data(), st.grp_ptr.size());
+    op->grp_col = upload(op, st.grp_col.data(), st.grp_col.size());
+    if (const char* env = std::getenv("AIMM_NEAR_CSR")) op->near_mfma = std::atoi(env) == 0;
     // macromodel column lists, r-major within each kind
     op->type_count.assign(a.n_types, 0);
     op->col_start.assign(a.n_types, 0);

@@ -48,6 +48,7 @@ struct PrecData {
   T* Wp = nullptr;           // [4][N * q3] projection weights, entry = n * q3 + p
   T* Wt = nullptr;           // [4][q3][N] interpolation weights
   cplx<T>* near = nullptr;   // pre-corrected near field
+  cplx<T>* grpA = nullptr;   // near field as dense row-group blocks
   cplx<T>* gt = nullptr;     // kernel spectrum, [Lx/2+1][Ly/2+1][nz]
   cplx<T>* tw_x = nullptr;
   cplx<T>* tw_y = nullptr;
@@ -98,7 +99,9 @@ struct aim_op {
   aimm::DeviceMem mem;
   int *sloc = nullptr, *node_ptr = nullptr, *node_ent = nullptr, *node_n = nullptr, *near_ptr = nullptr,
       *near_col = nullptr;
-  int* offsets_d = nullptr;  // [n_off][2] lattice offsets of the near-field blocks
+  int* offsets_d = nullptr;
+  int *grp_ptr = nullptr, *grp_col = nullptr;
+  bool near_mfma = true;  // [n_off][2] lattice offsets of the near-field blocks
   int *nbr = nullptr, *d_ptr = nullptr, *d_col = nullptr, *rev_x = nullptr, *rev_y = nullptr, *col_list = nullptr;
   aimm::PrecData<double> p64;
   aimm::PrecData<float> p32;

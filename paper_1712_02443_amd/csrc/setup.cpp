@@ -496,6 +496,34 @@ void build_setup(const SurfaceIn& s, const ArrayIn& a, Setup& out) {
     }
     out.near_ptr[n + 1] = int32_t(out.near_col.size());
   }
+  // row groups for the matrix-core near field
+  const int ng = (N + kNearGroup - 1) / kNearGroup;
+  out.grp_ptr.assign(ng + 1, 0);
+  out.grp_col.clear();
+  out.grp_A.clear();
+  for (int g = 0; g < ng; ++g) {
+    std::map<int32_t, int> col_index;
+    for (int i = 0; i < kNearGroup; ++i) {
+      const int n = g * kNearGroup + i;
+      if (n >= N) break;
+      for (int e = out.near_ptr[n]; e < out.near_ptr[n + 1]; ++e) col_index.emplace(out.near_col[e], 0);
+    }
+    int k = 0;
+    for (auto& kv : col_index) kv.second = k++;
+    const int kpad = (k + 3) / 4 * 4;
+    const size_t base = out.grp_col.size();
+    for (auto& kv : col_index) out.grp_col.push_back(kv.first);
+    // padding columns repeat a real column with zero coefficients
+    for (int p = k; p < kpad; ++p) out.grp_col.push_back(col_index.empty() ? 0 : col_index.begin()->first);
+    out.grp_A.resize(out.grp_col.size() * kNearGroup, cd(0.0));
+    for (int i = 0; i < kNearGroup; ++i) {
+      const int n = g * kNearGroup + i;
+      if (n >= N) break;
+      for (int e = out.near_ptr[n]; e < out.near_ptr[n + 1]; ++e)
+        out.grp_A[(base + col_index[out.near_col[e]]) * kNearGroup + i] = out.near_val[e];
+    }
+    out.grp_ptr[g + 1] = int32_t(out.grp_col.size());
+  }
 }
 
 void plane_wave_local(const SurfaceIn& s, double k, double theta, double phi, int pol,
