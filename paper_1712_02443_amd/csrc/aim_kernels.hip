@@ -300,11 +300,11 @@ __global__ void __launch_bounds__(256) k_near_mfma(const cplx<T>* __restrict__ u
   const cplx<T>* ur = uT + int64_t(r) * a.N * a.ne;
   typename M::acc_t accR = {}, accI = {};
   const int k0 = grp_ptr[g], k1 = grp_ptr[g + 1];
-#pragma unroll 2
+#pragma unroll 4
   for (int k = k0; k < k1; k += 4) {
     const int col = grp_col[k + kq];
-    const int o = col >> 16, np_ = col & 0xFFFF;
-    const int jx = ix + a.offsets[2 * o], jy = iy + a.offsets[2 * o + 1];
+    const int np_ = col & 0xFFFF;
+    const int jx = ix + ((col >> 16) & 0xFF) - 8, jy = iy + ((col >> 24) & 0xFF) - 8;
     const bool ok = validb && jx >= 0 && jx < a.px && jy >= 0 && jy < a.py;
     const cplx<T> bv = ok ? ur[int64_t(np_) * a.ne + jy * a.px + jx] : cmk<T>(0, 0);
     const cplx<T> av = grp_A[int64_t(k + kq) * kNearGroupDev + jcol];
@@ -351,42 +351,62 @@ __global__ void __launch_bounds__(256) k_interp(const cplx<T>* __restrict__ Phi,
   }
   __syncthreads();
   constexpr int q = QS, q3 = QS * QS * QS;
+  constexpr int kMaxTile = 4;
   const int64_t rows = int64_t(a.ne) * a.N;
-  for (int ty = 0; ty < a.TY; ++ty) {
-    const int iy = iy0 + ty;
-    if (iy >= a.py) break;
+  // elements of this tile, in order
+  int ne_t = 0;
+  int tm[kMaxTile], tox[kMaxTile], toy[kMaxTile];
+  for (int ty = 0; ty < a.TY; ++ty)
     for (int tx = 0; tx < a.TX; ++tx) {
-      const int ix = ix0 + tx;
-      if (ix >= a.px) break;
-      const int m = iy * a.px + ix;
-      const int64_t rowbase = int64_t(r) * rows + int64_t(m) * a.N;
+      const int ix = ix0 + tx, iy = iy0 + ty;
+      if (ix < a.px && iy < a.py && ne_t < kMaxTile) {
+        tm[ne_t] = iy * a.px + ix;
+        tox[ne_t] = tx * a.pitch;
+        toy[ne_t] = ty * a.pitch;
+        ++ne_t;
+      }
+    }
 #pragma unroll 1
-      for (int n = threadIdx.x; n < a.N; n += blockDim.x) {
-        const int ox = tx * a.pitch + a.sloc[3 * n], oy = ty * a.pitch + a.sloc[3 * n + 1], oz = a.sloc[3 * n + 2];
-        cplx<T> dx = cmk<T>(0, 0);
-        if (MODE == 0) {
-          const cplx<T>* xr = x + rowbase;
-          for (int e = a.d_ptr[n]; e < a.d_ptr[n + 1]; ++e) cfma(dx, d_val[e], xr[a.d_col[e]]);
-        }
-        cplx<T> acc = cmk<T>(0, 0);
+  for (int n = threadIdx.x; n < a.N; n += blockDim.x) {
+    const int sx = a.sloc[3 * n], sy = a.sloc[3 * n + 1], oz = a.sloc[3 * n + 2];
+    cplx<T> acc[kMaxTile];
+#pragma unroll
+    for (int e = 0; e < kMaxTile; ++e) acc[e] = cmk<T>(0, 0);
 #pragma unroll 1
-        for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < 4; ++p) {
+      T w[q3];
+#pragma unroll
+      for (int t = 0; t < q3; ++t) w[t] = Wt[(int64_t(p) * q3 + t) * a.N + n];
+      const T sg = p < 3 ? T(1) : T(a.sig_phi);
+      const cplx<T>* f = box + p * bx * run;
+#pragma unroll
+      for (int e = 0; e < kMaxTile; ++e) {
+        if (e < ne_t) {
           cplx<T> sacc = cmk<T>(0, 0);
-          const T* w = Wt + int64_t(p) * q3 * a.N + n;
-          const cplx<T>* f = box + p * bx * run;
 #pragma unroll
           for (int i = 0; i < q; ++i)
 #pragma unroll
             for (int j = 0; j < q; ++j) {
-              const cplx<T>* fr = f + ((ox + i) * by + (oy + j)) * bz + oz;
+              const cplx<T>* fr = f + ((tox[e] + sx + i) * by + (toy[e] + sy + j)) * bz + oz;
 #pragma unroll
-              for (int l = 0; l < q; ++l) cfmas(sacc, w[int64_t((i * q + j) * q + l) * a.N], fr[l]);
+              for (int l = 0; l < q; ++l) cfmas(sacc, w[(i * q + j) * q + l], fr[l]);
             }
-          cfmas(acc, p < 3 ? T(1) : T(a.sig_phi), sacc);
+          cfmas(acc[e], sg, sacc);
         }
-        cplx<T> out = cmk<T>(T(a.keta) * acc.im, -T(a.keta) * acc.re);  // -j k eta0 * acc
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kMaxTile; ++e) {
+      if (e < ne_t) {
+        const int64_t rowbase = int64_t(r) * rows + int64_t(tm[e]) * a.N;
+        cplx<T> out = cmk<T>(T(a.keta) * acc[e].im, -T(a.keta) * acc[e].re);  // -j k eta0 * acc
         if (MODE != 2) out = cadd(out, nf[rowbase + n]);
-        if (MODE == 0) out = csub(dx, out);
+        if (MODE == 0) {
+          const cplx<T>* xr = x + rowbase;
+          cplx<T> dx = cmk<T>(0, 0);
+          for (int k = a.d_ptr[n]; k < a.d_ptr[n + 1]; ++k) cfma(dx, d_val[k], xr[a.d_col[k]]);
+          out = csub(dx, out);
+        }
         y[rowbase + n] = out;
       }
     }
@@ -399,15 +419,17 @@ __global__ void __launch_bounds__(256) k_interp(const cplx<T>* __restrict__ Phi,
 // re*im + im*re).  A 64 x 64 output tile per workgroup (2 x 2 waves); M_t and X
 // tiles are staged in LDS; the output is written element-fastest, uT[r][i][m].
 
-template <typename T>
-__device__ __forceinline__ void gemm_tile_setup(const GemmArgs& a, int& t, int& c0, int* cols, int64_t* colbase) {
+// Tile: 64 rows x kGemmCols columns per workgroup of two waves (32 rows each).
+constexpr int kGemmCols = 32;
+
+__device__ __forceinline__ void gemm_tile_setup(const GemmArgs& a, int& t, int* cols, int64_t* colbase) {
   t = 0;
   int tile = blockIdx.x;
   while (t + 1 < a.n_types && tile >= a.tile_start[t + 1]) ++t;
   tile -= a.tile_start[t];
-  c0 = tile * 64;
+  const int c0 = tile * kGemmCols;
   const int ncols = a.R * a.type_count[t];
-  if (threadIdx.x < 64) {
+  if (threadIdx.x < kGemmCols) {
     const int c = c0 + threadIdx.x;
     const int col = c < ncols ? a.col_list[a.col_start[t] + c] : -1;
     cols[threadIdx.x] = col;
@@ -415,55 +437,82 @@ __device__ __forceinline__ void gemm_tile_setup(const GemmArgs& a, int& t, int& 
   }
 }
 
+// registers of one K-tile: A (KT x 64) and B (KT x kGemmCols) split over 128 threads
 template <typename T, int KT>
-__device__ __forceinline__ void gemm_load_tiles(const cplx<T>* Mt, const cplx<T>* X, int N, int i0, int k0,
-                                                const int* cols, cplx<T>* As, cplx<T>* Bs) {
-  for (int e = threadIdx.x; e < KT * 64; e += 256) {
-    const int k = e / 64, i = e - k * 64;
-    As[k * 64 + i] = (i0 + i < N && k0 + k < N) ? Mt[int64_t(k0 + k) * N + i0 + i] : cmk<T>(0, 0);
+struct GemmStage {
+  static constexpr int NA = KT * 64 / 128, NB = KT * kGemmCols / 128;
+  cplx<T> a[NA], b[NB];
+  __device__ __forceinline__ void load(const cplx<T>* Mt, const cplx<T>* X, int N, int i0, int k0, const int* cols) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = threadIdx.x + 128 * u;
+      const int k = e / 64, i = e % 64;
+      a[u] = (i0 + i < N && k0 + k < N) ? Mt[int64_t(k0 + k) * N + i0 + i] : cmk<T>(0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = threadIdx.x + 128 * u;
+      const int j = e / KT, k = e % KT;
+      const int c = cols[j];
+      b[u] = (c >= 0 && k0 + k < N) ? X[int64_t(c) * N + k0 + k] : cmk<T>(0, 0);
+    }
   }
-  for (int e = threadIdx.x; e < KT * 64; e += 256) {
-    const int j = e / KT, k = e - j * KT;
-    const int c = cols[j];
-    Bs[k * 64 + j] = (c >= 0 && k0 + k < N) ? X[int64_t(c) * N + k0 + k] : cmk<T>(0, 0);
+  __device__ __forceinline__ void store(cplx<T>* As, cplx<T>* Bs) const {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = threadIdx.x + 128 * u;
+      As[(e / 64) * 64 + (e % 64)] = a[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = threadIdx.x + 128 * u;
+      Bs[(e % KT) * kGemmCols + e / KT] = b[u];
+    }
   }
-}
+};
 
 template <typename T>
 __device__ __forceinline__ void gemm_store_rows(cplx<T>* U, const cplx<T>* Ct, int ldc, const int64_t* colbase, int N,
                                                 int ne, int row0, int nrows) {
-  const int jc = threadIdx.x % 64;
+  const int jc = threadIdx.x % kGemmCols;
   const int64_t cb = colbase[jc];
-  for (int rr = threadIdx.x / 64; rr < nrows; rr += 4) {
+  for (int rr = threadIdx.x / kGemmCols; rr < nrows; rr += 128 / kGemmCols) {
     const int gi = row0 + rr;
     if (cb >= 0 && gi < N) U[cb + int64_t(gi) * ne] = Ct[rr * ldc + jc];
   }
 }
 
-__global__ void __launch_bounds__(256) k_gemm_f32(const cplx<float>* __restrict__ M, const cplx<float>* __restrict__ X,
+// shared buffer: the K-tile of A and B, reused for the 64 x (kGemmCols + 1) output tile
+constexpr int gemm_smem_elems(int KT) {
+  return KT * (64 + kGemmCols) > 64 * (kGemmCols + 1) ? KT * (64 + kGemmCols) : 64 * (kGemmCols + 1);
+}
+
+__global__ void __launch_bounds__(128) k_gemm_f32(const cplx<float>* __restrict__ M, const cplx<float>* __restrict__ X,
                                                   cplx<float>* __restrict__ U, GemmArgs a) {
   constexpr int KT = 32;
-  __shared__ __align__(16) cplx<float> smem[2 * KT * 64];
-  __shared__ int cols[64];
-  __shared__ int64_t colbase[64];
+  __shared__ __align__(16) cplx<float> smem[gemm_smem_elems(KT)];
+  __shared__ int cols[kGemmCols];
+  __shared__ int64_t colbase[kGemmCols];
   cplx<float>* As = smem;
   cplx<float>* Bs = smem + KT * 64;
-  int t, c0;
-  gemm_tile_setup<float>(a, t, c0, cols, colbase);
+  int t;
+  gemm_tile_setup(a, t, cols, colbase);
   const int N = a.N, i0 = blockIdx.y * 64;
   const cplx<float>* Mt = M + int64_t(t) * N * N;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wi = wave & 1, wj = wave >> 1;
+  const int wi = threadIdx.x >> 6, lane = threadIdx.x & 63;
   f32x16 accR = {}, accI = {};
   __syncthreads();
+  GemmStage<float, KT> st;
+  st.load(Mt, X, N, i0, 0, cols);
   for (int k0 = 0; k0 < N; k0 += KT) {
-    gemm_load_tiles<float, KT>(Mt, X, N, i0, k0, cols, As, Bs);
+    st.store(As, Bs);
     __syncthreads();
-#pragma unroll 4
+    if (k0 + KT < N) st.load(Mt, X, N, i0, k0 + KT, cols);  // next tile in flight
+#pragma unroll
     for (int kk = 0; kk < KT; kk += 2) {
       const int k = kk + (lane >> 5);
       const cplx<float> av = As[k * 64 + wi * 32 + (lane & 31)];
-      const cplx<float> bv = Bs[k * 64 + wj * 32 + (lane & 31)];
+      const cplx<float> bv = Bs[k * kGemmCols + (lane & 31)];
       accR = __builtin_amdgcn_mfma_f32_32x32x2f32(av.re, bv.re, accR, 0, 0, 0);
       accR = __builtin_amdgcn_mfma_f32_32x32x2f32(-av.im, bv.im, accR, 0, 0, 0);
       accI = __builtin_amdgcn_mfma_f32_32x32x2f32(av.re, bv.im, accI, 0, 0, 0);
@@ -471,42 +520,39 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const cplx<float>* __restrict_
     }
     __syncthreads();
   }
-  cplx<float>* Ct = smem;  // [32][65]
-  for (int h = 0; h < 2; ++h) {
-    __syncthreads();
-    if (wi == h) {
+  cplx<float>* Ct = smem;  // [64][kGemmCols + 1]
+  static_assert(64 * (kGemmCols + 1) <= gemm_smem_elems(32), "output tile exceeds the shared buffer");
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int i = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);  // v_mfma_f32_32x32x2f32 output row
-        const int j = wj * 32 + (lane & 31);
-        Ct[i * 65 + j] = cmk<float>(accR[r], accI[r]);
-      }
-    }
-    __syncthreads();
-    gemm_store_rows<float>(U, Ct, 65, colbase, N, a.ne, i0 + 32 * h, 32);
+  for (int r = 0; r < 16; ++r) {
+    const int i = wi * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);  // v_mfma_f32_32x32x2f32 output row
+    Ct[i * (kGemmCols + 1) + (lane & 31)] = cmk<float>(accR[r], accI[r]);
   }
+  __syncthreads();
+  gemm_store_rows<float>(U, Ct, kGemmCols + 1, colbase, N, a.ne, i0, 64);
 }
 
-__global__ void __launch_bounds__(256) k_gemm_f64(const cplx<double>* __restrict__ M,
+__global__ void __launch_bounds__(128) k_gemm_f64(const cplx<double>* __restrict__ M,
                                                   const cplx<double>* __restrict__ X, cplx<double>* __restrict__ U,
                                                   GemmArgs a) {
   constexpr int KT = 16;
-  __shared__ __align__(16) cplx<double> smem[2 * KT * 64];
-  __shared__ int cols[64];
-  __shared__ int64_t colbase[64];
+  __shared__ __align__(16) cplx<double> smem[gemm_smem_elems(KT)];
+  __shared__ int cols[kGemmCols];
+  __shared__ int64_t colbase[kGemmCols];
   cplx<double>* As = smem;
   cplx<double>* Bs = smem + KT * 64;
-  int t, c0;
-  gemm_tile_setup<double>(a, t, c0, cols, colbase);
+  int t;
+  gemm_tile_setup(a, t, cols, colbase);
   const int N = a.N, i0 = blockIdx.y * 64;
   const cplx<double>* Mt = M + int64_t(t) * N * N;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wi = wave & 1, wj = wave >> 1;
+  const int wi = threadIdx.x >> 6, lane = threadIdx.x & 63;
   f64x4 accR[2][2] = {}, accI[2][2] = {};
   __syncthreads();
+  GemmStage<double, KT> st;
+  st.load(Mt, X, N, i0, 0, cols);
   for (int k0 = 0; k0 < N; k0 += KT) {
-    gemm_load_tiles<double, KT>(Mt, X, N, i0, k0, cols, As, Bs);
+    st.store(As, Bs);
     __syncthreads();
+    if (k0 + KT < N) st.load(Mt, X, N, i0, k0 + KT, cols);
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 4) {
       const int k = kk + (lane >> 4);
@@ -514,7 +560,7 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const cplx<double>* __restrict
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         av[q] = As[k * 64 + wi * 32 + q * 16 + (lane & 15)];
-        bv[q] = Bs[k * 64 + wj * 32 + q * 16 + (lane & 15)];
+        bv[q] = Bs[k * kGemmCols + q * 16 + (lane & 15)];
       }
 #pragma unroll
       for (int ti = 0; ti < 2; ++ti)
@@ -528,24 +574,19 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const cplx<double>* __restrict
     }
     __syncthreads();
   }
-  cplx<double>* Ct = smem;  // [32][64]
-  for (int h = 0; h < 2; ++h) {
-    __syncthreads();
-    if (wi == h) {
+  cplx<double>* Ct = smem;  // [64][kGemmCols + 1]
+  static_assert(64 * (kGemmCols + 1) <= gemm_smem_elems(16), "output tile exceeds the shared buffer");
 #pragma unroll
-      for (int ti = 0; ti < 2; ++ti)
+  for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj)
+    for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = ti * 16 + (lane >> 4) + 4 * r;  // v_mfma_f64_16x16x4f64 output row
-            const int j = wj * 32 + tj * 16 + (lane & 15);
-            Ct[i * 64 + j] = cmk<double>(accR[ti][tj][r], accI[ti][tj][r]);
-          }
-    }
-    __syncthreads();
-    gemm_store_rows<double>(U, Ct, 64, colbase, N, a.ne, i0 + 32 * h, 32);
-  }
+      for (int r = 0; r < 4; ++r) {
+        const int i = wi * 32 + ti * 16 + (lane >> 4) + 4 * r;  // v_mfma_f64_16x16x4f64 output row
+        Ct[i * (kGemmCols + 1) + tj * 16 + (lane & 15)] = cmk<double>(accR[ti][tj][r], accI[ti][tj][r]);
+      }
+  __syncthreads();
+  gemm_store_rows<double>(U, Ct, kGemmCols + 1, colbase, N, a.ne, i0, 64);
 }
 
 // ---- setup helpers -----------------------------------------------------------------
@@ -693,7 +734,7 @@ template <typename T>
 hipError_t launch_macro(const cplx<T>* M, const cplx<T>* X, cplx<T>* U, const GemmArgs& a, hipStream_t s) {
   const int tiles = a.tile_start[a.n_types];  // host copy of the tile prefix sums
   if (tiles == 0) return hipSuccess;
-  const dim3 g(tiles, (a.N + 63) / 64), b(256);
+  const dim3 g(tiles, (a.N + 63) / 64), b(128);
   if constexpr (sizeof(T) == sizeof(float))
     hipLaunchKernelGGL(k_gemm_f32, g, b, 0, s, reinterpret_cast<const cplx<float>*>(M),
                        reinterpret_cast<const cplx<float>*>(X), reinterpret_cast<cplx<float>*>(U), a);

@@ -59,6 +59,8 @@ inline size_t interp_lds_bytes(const InterpArgs& a, size_t elem) {
   return 4 * bx * by * a.nz * elem;
 }
 
+constexpr int kGemmColsHost = 32;  // output columns per macromodel GEMM workgroup
+
 struct GemmArgs {
   int N, R, n_types, ne;
   int tile_start[kMaxTypes + 1];

@@ -2,6 +2,7 @@
 // eq. MV_product1 and its parts.  GMRES lives in gmres.hip.
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <stdexcept>
 #include <string>
@@ -107,9 +108,13 @@ static void fill_prec(aim_op* op, PrecData<T>& P) {
   twiddles<T>(op->Ly, tw);
   P.tw_y = upload(op, tw.data(), tw.size());
   P.gt = op->mem.alloc<cplx<T>>(size_t(op->Lx / 2 + 1) * (op->Ly / 2 + 1) * st.nz);
-  // ky lines per workgroup in the spectrum pass: largest of 4, 2, 1 that fits LDS
+  // ky lines per workgroup in the spectrum pass: the widest allowed value whose
+  // workgroup fits LDS.  One line block (B = 1) measured fastest on the 400 x 400 grid
+  // (more workgroups in flight); AIMM_FFT_B raises the maximum.
+  int bmax = 1;
+  if (const char* env = std::getenv("AIMM_FFT_B")) bmax = std::max(1, std::atoi(env));
   P.B = 1;
-  for (int B : {4, 2}) {
+  for (int B = bmax; B >= 2; --B) {
     const size_t lds = sizeof(cplx<T>) * size_t(op->Lx) * (1 + B * st.nz);
     if (op->Ly % B == 0 && lds <= op->lds_max) {
       P.B = B;
@@ -197,10 +202,19 @@ static InterpArgs interp_args(aim_op* op, int R) {
   a.sloc = op->sloc;
   a.d_ptr = op->d_ptr;
   a.d_col = op->d_col;
-  // two elements per tile along x when the lattice is wide enough and the box fits
-  a.TX = op->arr.px >= 8 ? 2 : 1;
-  a.TY = 1;
-  if (interp_lds_bytes(a, sizeof(cplx<T>)) > op->lds_max) a.TX = 1;
+  // element tile of the interpolation workgroup: the projection weights are loaded
+  // once per tile, the tile's box of potentials must fit LDS
+  // (one element per workgroup measured fastest on the 32 x 32 array)
+  a.TX = op->interp_tx > 0 ? op->interp_tx : 1;
+  a.TY = op->interp_ty > 0 ? op->interp_ty : 1;
+  while (a.TX * a.TY > 4 || interp_lds_bytes(a, sizeof(cplx<T>)) > op->lds_max) {
+    if (a.TY > 1)
+      a.TY = 1;
+    else if (a.TX > 1)
+      a.TX = 1;
+    else
+      break;
+  }
   return a;
 }
 
@@ -215,7 +229,7 @@ static GemmArgs gemm_args(aim_op* op, int R) {
   for (int t = 0; t < op->n_types; ++t) {
     a.type_count[t] = op->type_count[t];
     a.col_start[t] = op->col_start[t];
-    a.tile_start[t + 1] = a.tile_start[t] + (R * op->type_count[t] + 63) / 64;
+    a.tile_start[t + 1] = a.tile_start[t] + (R * op->type_count[t] + kGemmColsHost - 1) / kGemmColsHost;
   }
   return a;
 }
@@ -406,6 +420,7 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
     op->grp_ptr = upload(op, st.grp_ptr.data(), st.grp_ptr.size());
     op->grp_col = upload(op, st.grp_col.data(), st.grp_col.size());
     if (const char* env = std::getenv("AIMM_NEAR_CSR")) op->near_mfma = std::atoi(env) == 0;
+    if (const char* env = std::getenv("AIMM_INTERP_TILE")) std::sscanf(env, "%dx%d", &op->interp_tx, &op->interp_ty);
     // macromodel column lists, r-major within each kind
     op->type_count.assign(a.n_types, 0);
     op->col_start.assign(a.n_types, 0);

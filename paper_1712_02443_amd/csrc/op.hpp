@@ -101,7 +101,8 @@ struct aim_op {
       *near_col = nullptr;
   int* offsets_d = nullptr;
   int *grp_ptr = nullptr, *grp_col = nullptr;
-  bool near_mfma = true;  // [n_off][2] lattice offsets of the near-field blocks
+  bool near_mfma = true;
+  int interp_tx = 0, interp_ty = 0;  // 0 = automatic  // [n_off][2] lattice offsets of the near-field blocks
   int *nbr = nullptr, *d_ptr = nullptr, *d_col = nullptr, *rev_x = nullptr, *rev_y = nullptr, *col_list = nullptr;
   aimm::PrecData<double> p64;
   aimm::PrecData<float> p32;

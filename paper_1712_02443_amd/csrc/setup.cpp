@@ -512,9 +512,15 @@ void build_setup(const SurfaceIn& s, const ArrayIn& a, Setup& out) {
     for (auto& kv : col_index) kv.second = k++;
     const int kpad = (k + 3) / 4 * 4;
     const size_t base = out.grp_col.size();
-    for (auto& kv : col_index) out.grp_col.push_back(kv.first);
+    // device form of a column: n' | (dx + 8) << 16 | (dy + 8) << 24 (lattice offset inline)
+    auto dev_col = [&](int32_t c) {
+      const int o = c >> 16, np_ = c & 0xFFFF;
+      return int32_t(np_ | ((out.offsets[2 * o] + 8) << 16) | ((out.offsets[2 * o + 1] + 8) << 24));
+    };
+    for (auto& kv : col_index) out.grp_col.push_back(dev_col(kv.first));
     // padding columns repeat a real column with zero coefficients
-    for (int p = k; p < kpad; ++p) out.grp_col.push_back(col_index.empty() ? 0 : col_index.begin()->first);
+    for (int p = k; p < kpad; ++p) out.grp_col.push_back(col_index.empty() ? int32_t((8 << 16) | (8 << 24))
+                                                                           : dev_col(col_index.begin()->first));
     out.grp_A.resize(out.grp_col.size() * kNearGroup, cd(0.0));
     for (int i = 0; i < kNearGroup; ++i) {
       const int n = g * kNearGroup + i;

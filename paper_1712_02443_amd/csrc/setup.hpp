@@ -42,7 +42,7 @@ struct Setup {
   // with the union of its columns (padded to a multiple of 4) and a dense coefficient
   // block A[k][i] = C[group row i][union column k]
   std::vector<int32_t> grp_ptr;      // [n_groups + 1] offsets into grp_col / grp_A (in columns)
-  std::vector<int32_t> grp_col;      // packed (o << 16) | n'
+  std::vector<int32_t> grp_col;      // packed n' | (dx + 8) << 16 | (dy + 8) << 24
   std::vector<cd> grp_A;             // [total columns][kNearGroup]
   std::vector<int32_t> node_ptr;     // [ex*ey*ez + 1] projection gather table by local node
   std::vector<int32_t> node_ent;     // packed n * q3 + p
