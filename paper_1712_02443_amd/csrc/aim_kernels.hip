@@ -14,6 +14,25 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// Strided copy global -> LDS with U loads in flight per thread (a plain strided loop
+// waits for each load before its store).  f(e) -> value, g(e, value) stores it.
+template <int U, typename T, typename Load, typename Store>
+__device__ __forceinline__ void batched_copy(int n, Load f, Store g) {
+  for (int base = threadIdx.x; base < n; base += U * blockDim.x) {
+    cplx<T> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * blockDim.x;
+      if (e < n) v[u] = f(e);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * blockDim.x;
+      if (e < n) g(e, v[u]);
+    }
+  }
+}
+
 // ---- step (i): projection, owner-computes gather --------------------------------
 // Grid node g is written by exactly one element (its owner: the element whose
 // pitch-wide home cell contains g, the last row/column owning the tail).  The owner
@@ -95,10 +114,12 @@ __global__ void __launch_bounds__(256) k_fft_y_fwd(const cplx<T>* in, cplx<T>* o
   const int64_t plane = blockIdx.x;
   const cplx<T>* src = in + plane * int64_t(ny_in) * nz;
   for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = twg[i];
-  for (int e = threadIdx.x; e < ny_in * nz; e += blockDim.x) {
-    const int y = e / nz, z = e - y * nz;
-    buf[z * ld + y] = src[e];
-  }
+  batched_copy<8, T>(
+      ny_in * nz, [&](int e) { return src[e]; },
+      [&](int e, cplx<T> v) {
+        const int y = e / nz, z = e - y * nz;
+        buf[z * ld + y] = v;
+      });
   for (int e = threadIdx.x; e < (L - ny_in) * nz; e += blockDim.x) {
     const int z = e / (L - ny_in), y = ny_in + (e - z * (L - ny_in));
     buf[z * ld + y] = cmk<T>(0, 0);
@@ -133,10 +154,16 @@ __global__ void __launch_bounds__(256) k_fft_x(const cplx<T>* in, cplx<T>* out, 
   const cplx<T>* src = in + plane * int64_t(nx_in) * row + int64_t(kb) * lines;
   cplx<T>* dst = out + plane * int64_t(nx_in) * row + int64_t(kb) * lines;
   for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = twg[i];
-  for (int e = threadIdx.x; e < nx_in * lines; e += blockDim.x) {
-    const int x = e / lines, l = e - x * lines;
-    buf[l * ld + x] = src[int64_t(x) * row + l];
-  }
+  batched_copy<8, T>(
+      nx_in * lines,
+      [&](int e) {
+        const int x = e / lines, l = e - x * lines;
+        return src[int64_t(x) * row + l];
+      },
+      [&](int e, cplx<T> v) {
+        const int x = e / lines, l = e - x * lines;
+        buf[l * ld + x] = v;
+      });
   for (int e = threadIdx.x; e < (L - nx_in) * lines; e += blockDim.x) {
     const int l = e / (L - nx_in), x = nx_in + (e - l * (L - nx_in));
     buf[l * ld + x] = cmk<T>(0, 0);
@@ -189,10 +216,12 @@ __global__ void __launch_bounds__(256) k_fft_y_inv(const cplx<T>* in, cplx<T>* o
   const int64_t plane = blockIdx.x;
   const cplx<T>* src = in + plane * int64_t(L) * nz;
   for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = twg[i];
-  for (int e = threadIdx.x; e < L * nz; e += blockDim.x) {
-    const int y = e / nz, z = e - y * nz;
-    buf[z * ld + y] = src[e];
-  }
+  batched_copy<8, T>(
+      L * nz, [&](int e) { return src[e]; },
+      [&](int e, cplx<T> v) {
+        const int y = e / nz, z = e - y * nz;
+        buf[z * ld + y] = v;
+      });
   __syncthreads();
   lds_fft_inv(buf, ld, nz, P, tw);
   cplx<T>* dst = out + plane * int64_t(ny) * nz;
@@ -300,18 +329,39 @@ __global__ void __launch_bounds__(256) k_near_mfma(const cplx<T>* __restrict__ u
   const cplx<T>* ur = uT + int64_t(r) * a.N * a.ne;
   typename M::acc_t accR = {}, accI = {};
   const int k0 = grp_ptr[g], k1 = grp_ptr[g + 1];
-#pragma unroll 4
-  for (int k = k0; k < k1; k += 4) {
-    const int col = grp_col[k + kq];
-    const int np_ = col & 0xFFFF;
-    const int jx = ix + ((col >> 16) & 0xFF) - 8, jy = iy + ((col >> 24) & 0xFF) - 8;
-    const bool ok = validb && jx >= 0 && jx < a.px && jy >= 0 && jy < a.py;
-    const cplx<T> bv = ok ? ur[int64_t(np_) * a.ne + jy * a.px + jx] : cmk<T>(0, 0);
-    const cplx<T> av = grp_A[int64_t(k + kq) * kNearGroupDev + jcol];
-    accR = M::mma(av.re, bv.re, accR);
-    accR = M::mma(-av.im, bv.im, accR);
-    accI = M::mma(av.re, bv.im, accI);
-    accI = M::mma(av.im, bv.re, accI);
+  constexpr int P = 4;  // K-steps of 4 columns per batch; the next batch is loaded ahead
+  auto fetch = [&](int k, cplx<T>& av, cplx<T>& bv) {
+    if (k < k1) {
+      const int col = grp_col[k + kq];
+      const int np_ = col & 0xFFFF;
+      const int jx = ix + ((col >> 16) & 0xFF) - 8, jy = iy + ((col >> 24) & 0xFF) - 8;
+      const bool ok = validb && jx >= 0 && jx < a.px && jy >= 0 && jy < a.py;
+      bv = ok ? ur[int64_t(np_) * a.ne + jy * a.px + jx] : cmk<T>(0, 0);
+      av = grp_A[int64_t(k + kq) * kNearGroupDev + jcol];
+    } else {
+      av = cmk<T>(0, 0);
+      bv = cmk<T>(0, 0);
+    }
+  };
+  cplx<T> ca[P], cb[P];
+#pragma unroll
+  for (int u = 0; u < P; ++u) fetch(k0 + 4 * u, ca[u], cb[u]);
+  for (int k = k0; k < k1; k += 4 * P) {
+    cplx<T> na[P], nb[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) fetch(k + 4 * P + 4 * u, na[u], nb[u]);
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      accR = M::mma(ca[u].re, cb[u].re, accR);
+      accR = M::mma(-ca[u].im, cb[u].im, accR);
+      accI = M::mma(ca[u].re, cb[u].im, accI);
+      accI = M::mma(ca[u].im, cb[u].re, accI);
+    }
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      ca[u] = na[u];
+      cb[u] = nb[u];
+    }
   }
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) tile[mfma16_row<T>(lane, rr)][wave * 16 + jcol] = cmk<T>(accR[rr], accI[rr]);
@@ -343,12 +393,15 @@ __global__ void __launch_bounds__(256) k_interp(const cplx<T>* __restrict__ Phi,
   const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
   const cplx<T>* ph = Phi + int64_t(r) * 4 * nodes;
   const int run = by * bz;  // contiguous run per (psi, x)
-  for (int idx = threadIdx.x; idx < 4 * bx * run; idx += blockDim.x) {
-    const int p = idx / (bx * run);
-    const int rem = idx - p * bx * run;
-    const int lx = rem / run, k = rem - lx * run;
-    box[idx] = ph[p * nodes + (int64_t(gx0 + lx) * a.ny + gy0) * a.nz + k];
-  }
+  batched_copy<12, T>(
+      4 * bx * run,
+      [&](int idx) {
+        const int p = idx / (bx * run);
+        const int rem = idx - p * bx * run;
+        const int lx = rem / run, k = rem - lx * run;
+        return ph[p * nodes + (int64_t(gx0 + lx) * a.ny + gy0) * a.nz + k];
+      },
+      [&](int idx, cplx<T> v) { box[idx] = v; });
   __syncthreads();
   constexpr int q = QS, q3 = QS * QS * QS;
   constexpr int kMaxTile = 4;
@@ -419,8 +472,12 @@ __global__ void __launch_bounds__(256) k_interp(const cplx<T>* __restrict__ Phi,
 // re*im + im*re).  A 64 x 64 output tile per workgroup (2 x 2 waves); M_t and X
 // tiles are staged in LDS; the output is written element-fastest, uT[r][i][m].
 
-// Tile: 64 rows x kGemmCols columns per workgroup of two waves (32 rows each).
+// Tile: 32 rows x kGemmCols columns per workgroup; its four waves split K in four
+// contiguous ranges and read their MFMA operands straight from global memory (A:
+// two 32-value row segments per step, B: per-column runs that stay in L1); the four
+// partial tiles are summed in LDS in a fixed order.
 constexpr int kGemmCols = 32;
+constexpr int kGemmRows = 32;
 
 __device__ __forceinline__ void gemm_tile_setup(const GemmArgs& a, int& t, int* cols, int64_t* colbase) {
   t = 0;
@@ -437,156 +494,142 @@ __device__ __forceinline__ void gemm_tile_setup(const GemmArgs& a, int& t, int* 
   }
 }
 
-// registers of one K-tile: A (KT x 64) and B (KT x kGemmCols) split over 128 threads
-template <typename T, int KT>
-struct GemmStage {
-  static constexpr int NA = KT * 64 / 128, NB = KT * kGemmCols / 128;
-  cplx<T> a[NA], b[NB];
-  __device__ __forceinline__ void load(const cplx<T>* Mt, const cplx<T>* X, int N, int i0, int k0, const int* cols) {
-#pragma unroll
-    for (int u = 0; u < NA; ++u) {
-      const int e = threadIdx.x + 128 * u;
-      const int k = e / 64, i = e % 64;
-      a[u] = (i0 + i < N && k0 + k < N) ? Mt[int64_t(k0 + k) * N + i0 + i] : cmk<T>(0, 0);
-    }
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int e = threadIdx.x + 128 * u;
-      const int j = e / KT, k = e % KT;
-      const int c = cols[j];
-      b[u] = (c >= 0 && k0 + k < N) ? X[int64_t(c) * N + k0 + k] : cmk<T>(0, 0);
-    }
-  }
-  __device__ __forceinline__ void store(cplx<T>* As, cplx<T>* Bs) const {
-#pragma unroll
-    for (int u = 0; u < NA; ++u) {
-      const int e = threadIdx.x + 128 * u;
-      As[(e / 64) * 64 + (e % 64)] = a[u];
-    }
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int e = threadIdx.x + 128 * u;
-      Bs[(e % KT) * kGemmCols + e / KT] = b[u];
-    }
-  }
-};
-
+// sum the four partial tiles and write rows i0 .. i0+31 element-fastest
 template <typename T>
-__device__ __forceinline__ void gemm_store_rows(cplx<T>* U, const cplx<T>* Ct, int ldc, const int64_t* colbase, int N,
-                                                int ne, int row0, int nrows) {
-  const int jc = threadIdx.x % kGemmCols;
-  const int64_t cb = colbase[jc];
-  for (int rr = threadIdx.x / kGemmCols; rr < nrows; rr += 128 / kGemmCols) {
-    const int gi = row0 + rr;
-    if (cb >= 0 && gi < N) U[cb + int64_t(gi) * ne] = Ct[rr * ldc + jc];
+__device__ __forceinline__ void gemm_reduce_store(const cplx<T>* part, cplx<T>* U, const int64_t* colbase, int N, int ne,
+                                                  int i0) {
+  for (int idx = threadIdx.x; idx < kGemmRows * kGemmCols; idx += blockDim.x) {
+    const int row = idx / kGemmCols, col = idx % kGemmCols;
+    cplx<T> acc = part[row * (kGemmCols + 1) + col];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) acc = cadd(acc, part[(w * kGemmRows + row) * (kGemmCols + 1) + col]);
+    const int64_t cb = colbase[col];
+    if (cb >= 0 && i0 + row < N) U[cb + int64_t(i0 + row) * ne] = acc;
   }
 }
 
-// shared buffer: the K-tile of A and B, reused for the 64 x (kGemmCols + 1) output tile
-constexpr int gemm_smem_elems(int KT) {
-  return KT * (64 + kGemmCols) > 64 * (kGemmCols + 1) ? KT * (64 + kGemmCols) : 64 * (kGemmCols + 1);
-}
-
-__global__ void __launch_bounds__(128) k_gemm_f32(const cplx<float>* __restrict__ M, const cplx<float>* __restrict__ X,
+__global__ void __launch_bounds__(256) k_gemm_f32(const cplx<float>* __restrict__ M, const cplx<float>* __restrict__ X,
                                                   cplx<float>* __restrict__ U, GemmArgs a) {
-  constexpr int KT = 32;
-  __shared__ __align__(16) cplx<float> smem[gemm_smem_elems(KT)];
+  __shared__ cplx<float> part[4 * kGemmRows * (kGemmCols + 1)];
   __shared__ int cols[kGemmCols];
   __shared__ int64_t colbase[kGemmCols];
-  cplx<float>* As = smem;
-  cplx<float>* Bs = smem + KT * 64;
   int t;
   gemm_tile_setup(a, t, cols, colbase);
-  const int N = a.N, i0 = blockIdx.y * 64;
-  const cplx<float>* Mt = M + int64_t(t) * N * N;
-  const int wi = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  f32x16 accR = {}, accI = {};
   __syncthreads();
-  GemmStage<float, KT> st;
-  st.load(Mt, X, N, i0, 0, cols);
-  for (int k0 = 0; k0 < N; k0 += KT) {
-    st.store(As, Bs);
-    __syncthreads();
-    if (k0 + KT < N) st.load(Mt, X, N, i0, k0 + KT, cols);  // next tile in flight
+  const int N = a.N, i0 = blockIdx.y * kGemmRows;
+  const cplx<float>* Mt = M + int64_t(t) * N * N;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = lane & 31, kk = lane >> 5;
+  const int colj = cols[lane & 31];
+  const bool rowok = i0 + i < N;
+  const int kq = ((N + 7) / 8) * 2;  // per-wave range, a multiple of the K step (2)
+  const int kb = w * kq, ke = min(N, kb + kq);
+  const cplx<float>* xc = X + (colj >= 0 ? int64_t(colj) * N : 0);
+  auto fetch = [&](int k, cplx<float>& av, cplx<float>& bv) {
+    const int kk2 = k + kk;
+    av = (rowok && kk2 < ke) ? Mt[int64_t(kk2) * N + i0 + i] : cmk<float>(0, 0);
+    bv = (colj >= 0 && kk2 < ke) ? xc[kk2] : cmk<float>(0, 0);
+  };
+  f32x16 accR = {}, accI = {};
+  constexpr int P = 8;
+  cplx<float> ca[P], cb[P];
 #pragma unroll
-    for (int kk = 0; kk < KT; kk += 2) {
-      const int k = kk + (lane >> 5);
-      const cplx<float> av = As[k * 64 + wi * 32 + (lane & 31)];
-      const cplx<float> bv = Bs[k * kGemmCols + (lane & 31)];
-      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(av.re, bv.re, accR, 0, 0, 0);
-      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(-av.im, bv.im, accR, 0, 0, 0);
-      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(av.re, bv.im, accI, 0, 0, 0);
-      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(av.im, bv.re, accI, 0, 0, 0);
+  for (int u = 0; u < P; ++u) fetch(kb + 2 * u, ca[u], cb[u]);
+  for (int k = kb; k < ke; k += 2 * P) {
+    cplx<float> na[P], nb[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) fetch(k + 2 * P + 2 * u, na[u], nb[u]);
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[u].re, cb[u].re, accR, 0, 0, 0);
+      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(-ca[u].im, cb[u].im, accR, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[u].re, cb[u].im, accI, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[u].im, cb[u].re, accI, 0, 0, 0);
     }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      ca[u] = na[u];
+      cb[u] = nb[u];
+    }
   }
-  cplx<float>* Ct = smem;  // [64][kGemmCols + 1]
-  static_assert(64 * (kGemmCols + 1) <= gemm_smem_elems(32), "output tile exceeds the shared buffer");
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const int i = wi * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);  // v_mfma_f32_32x32x2f32 output row
-    Ct[i * (kGemmCols + 1) + (lane & 31)] = cmk<float>(accR[r], accI[r]);
+    const int row = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);  // v_mfma_f32_32x32x2f32 output row
+    part[(w * kGemmRows + row) * (kGemmCols + 1) + (lane & 31)] = cmk<float>(accR[r], accI[r]);
   }
   __syncthreads();
-  gemm_store_rows<float>(U, Ct, kGemmCols + 1, colbase, N, a.ne, i0, 64);
+  gemm_reduce_store<float>(part, U, colbase, N, a.ne, i0);
 }
 
-__global__ void __launch_bounds__(128) k_gemm_f64(const cplx<double>* __restrict__ M,
+__global__ void __launch_bounds__(256) k_gemm_f64(const cplx<double>* __restrict__ M,
                                                   const cplx<double>* __restrict__ X, cplx<double>* __restrict__ U,
                                                   GemmArgs a) {
-  constexpr int KT = 16;
-  __shared__ __align__(16) cplx<double> smem[gemm_smem_elems(KT)];
+  __shared__ cplx<double> part[4 * kGemmRows * (kGemmCols + 1)];
   __shared__ int cols[kGemmCols];
   __shared__ int64_t colbase[kGemmCols];
-  cplx<double>* As = smem;
-  cplx<double>* Bs = smem + KT * 64;
   int t;
   gemm_tile_setup(a, t, cols, colbase);
-  const int N = a.N, i0 = blockIdx.y * 64;
-  const cplx<double>* Mt = M + int64_t(t) * N * N;
-  const int wi = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  f64x4 accR[2][2] = {}, accI[2][2] = {};
   __syncthreads();
-  GemmStage<double, KT> st;
-  st.load(Mt, X, N, i0, 0, cols);
-  for (int k0 = 0; k0 < N; k0 += KT) {
-    st.store(As, Bs);
-    __syncthreads();
-    if (k0 + KT < N) st.load(Mt, X, N, i0, k0 + KT, cols);
+  const int N = a.N, i0 = blockIdx.y * kGemmRows;
+  const cplx<double>* Mt = M + int64_t(t) * N * N;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l16 = lane & 15, kk = lane >> 4;
+  int colq[2];
+  bool rowok[2];
 #pragma unroll
-    for (int kk = 0; kk < KT; kk += 4) {
-      const int k = kk + (lane >> 4);
-      cplx<double> av[2], bv[2];
+  for (int q = 0; q < 2; ++q) {
+    colq[q] = cols[q * 16 + l16];
+    rowok[q] = i0 + q * 16 + l16 < N;
+  }
+  const int kq = ((N + 15) / 16) * 4;  // per-wave range, a multiple of the K step (4)
+  const int kb = w * kq, ke = min(N, kb + kq);
+  auto fetch = [&](int k, cplx<double>* av, cplx<double>* bv) {
+    const int kk2 = k + kk;
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        av[q] = As[k * 64 + wi * 32 + q * 16 + (lane & 15)];
-        bv[q] = Bs[k * kGemmCols + q * 16 + (lane & 15)];
-      }
+    for (int q = 0; q < 2; ++q) {
+      av[q] = (rowok[q] && kk2 < ke) ? Mt[int64_t(kk2) * N + i0 + q * 16 + l16] : cmk<double>(0, 0);
+      bv[q] = (colq[q] >= 0 && kk2 < ke) ? X[int64_t(colq[q]) * N + kk2] : cmk<double>(0, 0);
+    }
+  };
+  f64x4 accR[2][2] = {}, accI[2][2] = {};
+  constexpr int P = 4;
+  cplx<double> ca[P][2], cb[P][2];
+#pragma unroll
+  for (int u = 0; u < P; ++u) fetch(kb + 4 * u, ca[u], cb[u]);
+  for (int k = kb; k < ke; k += 4 * P) {
+    cplx<double> na[P][2], nb[P][2];
+#pragma unroll
+    for (int u = 0; u < P; ++u) fetch(k + 4 * P + 4 * u, na[u], nb[u]);
+#pragma unroll
+    for (int u = 0; u < P; ++u)
 #pragma unroll
       for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
         for (int tj = 0; tj < 2; ++tj) {
-          accR[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti].re, bv[tj].re, accR[ti][tj], 0, 0, 0);
-          accR[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[ti].im, bv[tj].im, accR[ti][tj], 0, 0, 0);
-          accI[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti].re, bv[tj].im, accI[ti][tj], 0, 0, 0);
-          accI[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti].im, bv[tj].re, accI[ti][tj], 0, 0, 0);
+          accR[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[u][ti].re, cb[u][tj].re, accR[ti][tj], 0, 0, 0);
+          accR[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ca[u][ti].im, cb[u][tj].im, accR[ti][tj], 0, 0, 0);
+          accI[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[u][ti].re, cb[u][tj].im, accI[ti][tj], 0, 0, 0);
+          accI[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[u][ti].im, cb[u][tj].re, accI[ti][tj], 0, 0, 0);
         }
-    }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < P; ++u)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        ca[u][q] = na[u][q];
+        cb[u][q] = nb[u][q];
+      }
   }
-  cplx<double>* Ct = smem;  // [64][kGemmCols + 1]
-  static_assert(64 * (kGemmCols + 1) <= gemm_smem_elems(16), "output tile exceeds the shared buffer");
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = wi * 32 + ti * 16 + (lane >> 4) + 4 * r;  // v_mfma_f64_16x16x4f64 output row
-        Ct[i * (kGemmCols + 1) + tj * 16 + (lane & 15)] = cmk<double>(accR[ti][tj][r], accI[ti][tj][r]);
+        const int row = ti * 16 + (lane >> 4) + 4 * r;  // v_mfma_f64_16x16x4f64 output row
+        part[(w * kGemmRows + row) * (kGemmCols + 1) + tj * 16 + l16] = cmk<double>(accR[ti][tj][r], accI[ti][tj][r]);
       }
   __syncthreads();
-  gemm_store_rows<double>(U, Ct, kGemmCols + 1, colbase, N, a.ne, i0, 64);
+  gemm_reduce_store<double>(part, U, colbase, N, a.ne, i0);
 }
 
 // ---- setup helpers -----------------------------------------------------------------
@@ -734,7 +777,7 @@ template <typename T>
 hipError_t launch_macro(const cplx<T>* M, const cplx<T>* X, cplx<T>* U, const GemmArgs& a, hipStream_t s) {
   const int tiles = a.tile_start[a.n_types];  // host copy of the tile prefix sums
   if (tiles == 0) return hipSuccess;
-  const dim3 g(tiles, (a.N + 63) / 64), b(128);
+  const dim3 g(tiles, (a.N + kGemmRows - 1) / kGemmRows), b(256);
   if constexpr (sizeof(T) == sizeof(float))
     hipLaunchKernelGGL(k_gemm_f32, g, b, 0, s, reinterpret_cast<const cplx<float>*>(M),
                        reinterpret_cast<const cplx<float>*>(X), reinterpret_cast<cplx<float>*>(U), a);
