@@ -88,6 +88,9 @@ def main() -> int:
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solves")
+    ap.add_argument("--profile-products", type=int, default=0,
+                    help="only run this many FP32 and FP64 products and a 512 MiB device copy "
+                         "(the copy calibrates hardware byte counters), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -112,8 +115,24 @@ def main() -> int:
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     info = op.info()
+    if args.profile_products:
+        x64 = torch.from_numpy(wl.test_vectors(1)).to("cuda")
+        x32 = x64.to(torch.complex64)
+        for xv, prec in ((x32, AIM_MIXED), (x64, AIM_FP64)):
+            y = torch.empty_like(xv)
+            for _ in range(args.profile_products):
+                op.matvec(xv, precision=prec, out=y)
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")  # 512 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] profiled {args.profile_products} products per precision and a 536870912-byte copy",
+              file=sys.stderr, flush=True)
+        return 0
     b = op.plane_wave_rhs(wl.theta, wl.phi, wl.pol)
-    solve_kw = dict(restart=args.restart, tol=args.tol, max_iters=5000)
+    # convergence flags are read by the host every 5 iterations (the result does not
+    # depend on it: each right-hand side stops at its own first converged column)
+    solve_kw = dict(restart=args.restart, tol=args.tol, max_iters=5000, check_every=5)
 
     def solve(prec):
         x, st, code = op.gmres(b, precision=prec, **solve_kw)

@@ -64,7 +64,22 @@ __global__ void __launch_bounds__(256) k_project(const cplx<T>* __restrict__ uT,
       const int e0 = a.node_ptr[node], e1 = a.node_ptr[node + 1];
       const bool ok = ix - dx >= 0 && iy - dy >= 0;
       const int ms = m - dx - dy * a.px;
-      for (int e = e0; e < e1; ++e) {
+      int e = e0;
+      for (; e + 4 <= e1; e += 4) {
+        int ent[4];
+        cplx<T> v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          ent[u] = a.node_ent[e + u];
+          const int n = a.node_n[e + u];
+          v[u] = ok ? ur[int64_t(n) * a.ne + ms] : cmk<T>(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int p = 0; p < 4; ++p) cfmas(acc[p], Wp[p * NQ + ent[u]], v[u]);
+      }
+      for (; e < e1; ++e) {
         const int ent = a.node_ent[e];
         const int n = a.node_n[e];
         const cplx<T> v = ok ? ur[int64_t(n) * a.ne + ms] : cmk<T>(0, 0);
@@ -318,18 +333,22 @@ __global__ void __launch_bounds__(256) k_near_mfma(const cplx<T>* __restrict__ u
                                                    NearArgs a, const int* __restrict__ grp_ptr,
                                                    const int* __restrict__ grp_col,
                                                    const cplx<T>* __restrict__ grp_A) {
+  // four waves: two element halves (16 elements each) x two halves of the union columns
   using M = NearMfma<T>;
-  __shared__ cplx<T> tile[kNearGroupDev][65];
+  __shared__ cplx<T> tile[2][kNearGroupDev][33];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int mblk = blockIdx.x * 64, g = blockIdx.y, r = blockIdx.z;
+  const int eh = wave & 1, kh = wave >> 1;
+  const int mblk = blockIdx.x * 32, g = blockIdx.y, r = blockIdx.z;
   const int jcol = lane & 15, kq = lane >> 4;
-  const int mb = mblk + wave * 16 + jcol;
+  const int mb = mblk + eh * 16 + jcol;
   const bool validb = mb < a.ne;
   const int ix = mb % a.px, iy = mb / a.px;
   const cplx<T>* ur = uT + int64_t(r) * a.N * a.ne;
   typename M::acc_t accR = {}, accI = {};
-  const int k0 = grp_ptr[g], k1 = grp_ptr[g + 1];
-  constexpr int P = 4;  // K-steps of 4 columns per batch; the next batch is loaded ahead
+  const int g0 = grp_ptr[g], g1 = grp_ptr[g + 1];
+  const int half = ((g1 - g0) / 8) * 4;  // first half, a multiple of the K step (4)
+  const int k0 = kh == 0 ? g0 : g0 + half, k1 = kh == 0 ? g0 + half : g1;
+  constexpr int P = 4;  // K-steps per batch; the next batch is loaded ahead
   auto fetch = [&](int k, cplx<T>& av, cplx<T>& bv) {
     if (k < k1) {
       const int col = grp_col[k + kq];
@@ -364,12 +383,14 @@ __global__ void __launch_bounds__(256) k_near_mfma(const cplx<T>* __restrict__ u
     }
   }
 #pragma unroll
-  for (int rr = 0; rr < 4; ++rr) tile[mfma16_row<T>(lane, rr)][wave * 16 + jcol] = cmk<T>(accR[rr], accI[rr]);
+  for (int rr = 0; rr < 4; ++rr)
+    tile[kh][mfma16_row<T>(lane, rr)][eh * 16 + jcol] = cmk<T>(accR[rr], accI[rr]);
   __syncthreads();
   const int n0 = g * kNearGroupDev;
-  for (int idx = threadIdx.x; idx < 64 * kNearGroupDev; idx += 256) {
+  for (int idx = threadIdx.x; idx < 32 * kNearGroupDev; idx += 256) {
     const int mm = idx / kNearGroupDev, nn = idx - mm * kNearGroupDev;
-    if (mblk + mm < a.ne && n0 + nn < a.N) nf[(int64_t(r) * a.ne + mblk + mm) * a.N + n0 + nn] = tile[nn][mm];
+    if (mblk + mm < a.ne && n0 + nn < a.N)
+      nf[(int64_t(r) * a.ne + mblk + mm) * a.N + n0 + nn] = cadd(tile[0][nn][mm], tile[1][nn][mm]);
   }
 }
 
@@ -425,7 +446,7 @@ __global__ void __launch_bounds__(256) k_interp(const cplx<T>* __restrict__ Phi,
     cplx<T> acc[kMaxTile];
 #pragma unroll
     for (int e = 0; e < kMaxTile; ++e) acc[e] = cmk<T>(0, 0);
-#pragma unroll 1
+#pragma unroll(sizeof(T) == 4 ? 4 : 2)
     for (int p = 0; p < 4; ++p) {
       T w[q3];
 #pragma unroll
@@ -738,7 +759,7 @@ hipError_t launch_near(const cplx<T>* uT, cplx<T>* nf, const NearArgs& a, const 
   if (a.grp_A) {
     // element blocks fastest, so consecutive workgroups (spread over the XCDs) share
     // the rows of u they read
-    const dim3 g((a.ne + 63) / 64, (a.N + kNearGroupDev - 1) / kNearGroupDev, a.R);
+    const dim3 g((a.ne + 31) / 32, (a.N + kNearGroupDev - 1) / kNearGroupDev, a.R);
     hipLaunchKernelGGL(k_near_mfma<T>, g, dim3(256), 0, s, uT, nf, a, a.grp_ptr, a.grp_col,
                        reinterpret_cast<const cplx<T>*>(a.grp_A));
   } else {

@@ -170,6 +170,70 @@ __global__ void __launch_bounds__(kBS) k_update(const cplx<Tb>* __restrict__ V, 
   }
 }
 
+// First-pass update fused with the second pass's projections:
+//   w <- w - sum_i V_i h1_i,  then part <- chunk sums of conj(V_i) . w  (i < nv).
+// The second read of each V_i chunk follows the first closely and is served by the
+// caches.
+template <typename Tb>
+__global__ void __launch_bounds__(kBS) k_update_dots(const cplx<Tb>* __restrict__ V, cplx<double>* __restrict__ w,
+                                                     const cplx<double>* __restrict__ coef, int ldc,
+                                                     double* __restrict__ part, int64_t n, int nv, int R) {
+  extern __shared__ double wsum[];  // [nv][4 waves][2]
+  const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t base = int64_t(c) * kChunk;
+  const cplx<double>* cf = coef + int64_t(r) * ldc;
+  cplx<double> acc[kE];
+#pragma unroll
+  for (int e = 0; e < kE; ++e) {
+    const int64_t k = base + e * kBS + threadIdx.x;
+    acc[e] = k < n ? w[int64_t(r) * n + k] : cmk<double>(0, 0);
+  }
+  for (int i = 0; i < nv; ++i) {
+    const cplx<double> h = cf[i];
+    const cplx<Tb>* vi = V + (int64_t(i) * R + r) * n;
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+      const int64_t k = base + e * kBS + threadIdx.x;
+      const cplx<double> v = k < n ? up(vi[k]) : cmk<double>(0, 0);
+      acc[e].re -= v.re * h.re - v.im * h.im;
+      acc[e].im -= v.re * h.im + v.im * h.re;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < kE; ++e) {
+    const int64_t k = base + e * kBS + threadIdx.x;
+    if (k < n) w[int64_t(r) * n + k] = acc[e];
+  }
+  for (int i = 0; i < nv; ++i) {
+    const cplx<Tb>* vi = V + (int64_t(i) * R + r) * n;
+    double a = 0, b = 0;
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+      const int64_t k = base + e * kBS + threadIdx.x;
+      const cplx<double> v = k < n ? up(vi[k]) : cmk<double>(0, 0);
+      a += v.re * acc[e].re + v.im * acc[e].im;
+      b += v.re * acc[e].im - v.im * acc[e].re;
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) {
+      wsum[(i * 4 + wave) * 2] = a;
+      wsum[(i * 4 + wave) * 2 + 1] = b;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+    double a = 0, b = 0;
+    for (int q = 0; q < 4; ++q) {
+      a += wsum[(i * 4 + q) * 2];
+      b += wsum[(i * 4 + q) * 2 + 1];
+    }
+    part[((int64_t(r) * nv + i) * nch + c) * 2] = a;
+    part[((int64_t(r) * nv + i) * nch + c) * 2 + 1] = b;
+  }
+}
+
 // chunk partials of ||a - b||^2 (b may be null) and of the difference into out
 __global__ void __launch_bounds__(kBS) k_residual(const cplx<double>* __restrict__ a, const cplx<double>* __restrict__ b,
                                                   cplx<double>* __restrict__ out, double* part, int64_t n) {
@@ -396,8 +460,7 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
       const size_t dots_lds = sizeof(double) * 8 * nv;
       GM_LAUNCH(k_dots<Tb>, gch, bs, dots_lds, s, V, K.w, K.part, n, nv, R);
       GM_LAUNCH(k_reduce_dots, dim3(nv * R), b64, 0, s, K.part, K.hcol, nch, nv, R, m + 1, 0);
-      GM_LAUNCH(k_update<Tb>, gch, bs, 0, s, V, K.w, K.hcol, m + 1, K.part, n, nv, R, 0);
-      GM_LAUNCH(k_dots<Tb>, gch, bs, dots_lds, s, V, K.w, K.part, n, nv, R);
+      GM_LAUNCH(k_update_dots<Tb>, gch, bs, dots_lds, s, V, K.w, K.hcol, m + 1, K.part, n, nv, R);
       GM_LAUNCH(k_reduce_dots, dim3(nv * R), b64, 0, s, K.part, K.h2, nch, nv, R, m + 1, 0);
       GM_LAUNCH(k_update<Tb>, gch, bs, 0, s, V, K.w, K.h2, m + 1, K.part, n, nv, R, 1);
       GM_LAUNCH(k_finish_norm, dim3(R), b64, 0, s, K.part, K.scal, nch, R, 4);
