@@ -395,8 +395,8 @@ __global__ void __launch_bounds__(256) k_near_mfma(const cplx<T>* __restrict__ u
 }
 
 // ---- step (iii) + combine: one workgroup per tile of elements ---------------------
-// The tile's box of grid potentials (4 psi) is staged in LDS; every basis gathers its
-// (N_O+1)^3 nodes per psi from LDS.  MODE 0: y = D x - (v + nf); 1: y = v + nf;
+// The tile's box of grid potentials (4 psi) and, in MODE 0, the tile's input rows are
+// staged in LDS; every basis gathers its (N_O+1)^3 nodes per psi from LDS.  MODE 0: y = D x - (v + nf); 1: y = v + nf;
 // 2: y = v, with v = -j k eta0 [sum_{x,y,z} I_psi Phi_psi - k^-2 I_phi Phi_phi].
 template <typename T, int MODE, int QS>
 __global__ void __launch_bounds__(256) k_interp(const cplx<T>* __restrict__ Phi, const cplx<T>* __restrict__ nf,
@@ -423,8 +423,6 @@ __global__ void __launch_bounds__(256) k_interp(const cplx<T>* __restrict__ Phi,
         return ph[p * nodes + (int64_t(gx0 + lx) * a.ny + gy0) * a.nz + k];
       },
       [&](int idx, cplx<T> v) { box[idx] = v; });
-  __syncthreads();
-  constexpr int q = QS, q3 = QS * QS * QS;
   constexpr int kMaxTile = 4;
   const int64_t rows = int64_t(a.ne) * a.N;
   // elements of this tile, in order
@@ -440,6 +438,17 @@ __global__ void __launch_bounds__(256) k_interp(const cplx<T>* __restrict__ Phi,
         ++ne_t;
       }
     }
+  // the tile's input rows, for the D product
+  cplx<T>* xs = box + 4 * bx * run;
+  if constexpr (MODE == 0) {
+    for (int e = 0; e < ne_t; ++e) {
+      const cplx<T>* xr = x + int64_t(r) * rows + int64_t(tm[e]) * a.N;
+      batched_copy<4, T>(
+          a.N, [&](int idx) { return xr[idx]; }, [&](int idx, cplx<T> v) { xs[e * a.N + idx] = v; });
+    }
+  }
+  __syncthreads();
+  constexpr int q = QS, q3 = QS * QS * QS;
 #pragma unroll 1
   for (int n = threadIdx.x; n < a.N; n += blockDim.x) {
     const int sx = a.sloc[3 * n], sy = a.sloc[3 * n + 1], oz = a.sloc[3 * n + 2];
@@ -476,9 +485,14 @@ __global__ void __launch_bounds__(256) k_interp(const cplx<T>* __restrict__ Phi,
         cplx<T> out = cmk<T>(T(a.keta) * acc[e].im, -T(a.keta) * acc[e].re);  // -j k eta0 * acc
         if (MODE != 2) out = cadd(out, nf[rowbase + n]);
         if (MODE == 0) {
-          const cplx<T>* xr = x + rowbase;
+          // D row n: slot-major padded layout, so every slot's loads are independent
+          const cplx<T>* xe = xs + e * a.N;
           cplx<T> dx = cmk<T>(0, 0);
-          for (int k = a.d_ptr[n]; k < a.d_ptr[n + 1]; ++k) cfma(dx, d_val[k], xr[a.d_col[k]]);
+#pragma unroll 4
+          for (int sl = 0; sl < a.dmax; ++sl) {
+            const int64_t at = int64_t(sl) * a.N + n;
+            cfma(dx, d_val[at], xe[a.d_colT[at]]);
+          }
           out = csub(dx, out);
         }
         y[rowbase + n] = out;

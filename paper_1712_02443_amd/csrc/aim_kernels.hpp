@@ -50,13 +50,16 @@ struct InterpArgs {
   int TX, TY;  // elements per workgroup tile
   double keta, sig_phi;
   const int* sloc;
-  const int* d_ptr;
-  const int* d_col;
+  // D block, padded to dmax slots per row and stored slot-major: entry s of row n at
+  // s * N + n (padding: column n, value 0)
+  const int* d_colT;
+  int dmax;
 };
 
 inline size_t interp_lds_bytes(const InterpArgs& a, size_t elem) {
   const size_t bx = size_t(a.pitch) * (a.TX - 1) + a.ex, by = size_t(a.pitch) * (a.TY - 1) + a.ey;
-  return 4 * bx * by * a.nz * elem;
+  // the tile's potential box (4 psi), then the tile's input rows for the D product
+  return (4 * bx * by * a.nz + size_t(a.TX) * a.TY * a.N) * elem;
 }
 
 constexpr int kGemmColsHost = 32;  // output columns per macromodel GEMM workgroup

@@ -1,5 +1,6 @@
 // C ABI of the library: operator construction, the final-system product of
 // eq. MV_product1 and its parts.  GMRES lives in gmres.hip.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
@@ -200,8 +201,8 @@ static InterpArgs interp_args(aim_op* op, int R) {
   a.keta = op->arr.k * op->arr.eta;
   a.sig_phi = -1.0 / (op->arr.k * op->arr.k);
   a.sloc = op->sloc;
-  a.d_ptr = op->d_ptr;
-  a.d_col = op->d_col;
+  a.d_colT = op->d_colT;
+  a.dmax = op->d_max;
   // element tile of the interpolation workgroup: the projection weights are loaded
   // once per tile, the tile's box of potentials must fit LDS
   // (one element per workgroup measured fastest on the 32 x 32 array)
@@ -539,26 +540,30 @@ int aim_set_dmatrix(aim_op* op, int64_t nnz, const int32_t* rows, const int32_t*
     set_error("op was built without device data (aim_build_host)");
     return AIM_ESTATE;
   }
-  // CSR by row, columns in input order within a row
-  std::vector<int> ptr(N + 1, 0), col(nnz);
-  std::vector<cplx<double>> v64(nnz);
-  std::vector<cplx<float>> v32(nnz);
-  for (int64_t i = 0; i < nnz; ++i) ptr[rows[i] + 1]++;
-  for (int n = 0; n < N; ++n) ptr[n + 1] += ptr[n];
-  std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+  // padded row layout, slot-major: slot s of row n at s * N + n; entries keep their
+  // input order within a row, padding slots point at column n with value 0
+  std::vector<int> cnt(N, 0);
+  for (int64_t i = 0; i < nnz; ++i) cnt[rows[i]]++;
+  const int dmax = nnz > 0 ? *std::max_element(cnt.begin(), cnt.end()) : 0;
+  std::vector<int> colT(size_t(dmax) * N), fill(N, 0);
+  std::vector<cplx<double>> v64(size_t(dmax) * N, cplx<double>{0.0, 0.0});
+  std::vector<cplx<float>> v32(size_t(dmax) * N, cplx<float>{0.0f, 0.0f});
+  for (int sl = 0; sl < dmax; ++sl)
+    for (int n = 0; n < N; ++n) colT[size_t(sl) * N + n] = n;
   for (int64_t i = 0; i < nnz; ++i) {
-    const int at = fill[rows[i]]++;
-    col[at] = cols[i];
+    const size_t at = size_t(fill[rows[i]]++) * N + rows[i];
+    colT[at] = cols[i];
     v64[at].re = vals[2 * i];
     v64[at].im = vals[2 * i + 1];
     v32[at].re = float(vals[2 * i]);
     v32[at].im = float(vals[2 * i + 1]);
   }
   try {
-    op->d_ptr = upload(op, ptr.data(), ptr.size());
-    op->d_col = upload(op, col.data(), col.size());
-    op->p64.dval = upload(op, v64.data(), v64.size());
-    op->p32.dval = upload(op, v32.data(), v32.size());
+    if (dmax > 0) {
+      op->d_colT = upload(op, colT.data(), colT.size());
+      op->p64.dval = upload(op, v64.data(), v64.size());
+      op->p32.dval = upload(op, v32.data(), v32.size());
+    }
   } catch (const std::bad_alloc&) {
     set_error("device allocation failed");
     return AIM_ENOMEM;
@@ -566,6 +571,7 @@ int aim_set_dmatrix(aim_op* op, int64_t nnz, const int32_t* rows, const int32_t*
     set_error(e.what());
     return AIM_EDEVICE;
   }
+  op->d_max = dmax;
   op->d_nnz = nnz;
   op->d_set = true;
   return AIM_OK;

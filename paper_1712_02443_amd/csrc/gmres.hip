@@ -59,38 +59,83 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
   }
 }
 
-// part[((r * nv + i) * nch + c) * 2 + {0,1}] = sum over chunk c of conj(V_i[r]) . w[r], i < nv.
-// Each wave reduces its own partial per i with lane shuffles; one barrier at the end.
+constexpr int kIV = 4;  // basis vectors loaded together (independent loads in flight)
+
+// v[u][e] = V_{min(i0+u, nv-1)}[r][base + e kBS + tid] (zero past n)
 template <typename Tb>
-__global__ void __launch_bounds__(kBS) k_dots(const cplx<Tb>* __restrict__ V, const cplx<double>* __restrict__ w,
-                                              double* __restrict__ part, int64_t n, int nv, int R) {
-  extern __shared__ double wsum[];  // [nv][4 waves][2]
-  const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t base = int64_t(c) * kChunk;
-  cplx<double> wl[kE];
+__device__ __forceinline__ void load_batch(const cplx<Tb>* __restrict__ V, int i0, int nv, int r, int R, int64_t n,
+                                           int64_t base, cplx<Tb> (&v)[kIV][kE]) {
 #pragma unroll
-  for (int e = 0; e < kE; ++e) {
-    const int64_t k = base + e * kBS + threadIdx.x;
-    wl[e] = k < n ? w[int64_t(r) * n + k] : cmk<double>(0, 0);
-  }
-  for (int i = 0; i < nv; ++i) {
+  for (int u = 0; u < kIV; ++u) {
+    const int i = min(i0 + u, nv - 1);
     const cplx<Tb>* vi = V + (int64_t(i) * R + r) * n;
-    double a = 0, b = 0;
 #pragma unroll
     for (int e = 0; e < kE; ++e) {
       const int64_t k = base + e * kBS + threadIdx.x;
-      const cplx<double> v = k < n ? up(vi[k]) : cmk<double>(0, 0);
-      a += v.re * wl[e].re + v.im * wl[e].im;
-      b += v.re * wl[e].im - v.im * wl[e].re;
-    }
-    a = wave_sum(a);
-    b = wave_sum(b);
-    if (lane == 0) {
-      wsum[(i * 4 + wave) * 2] = a;
-      wsum[(i * 4 + wave) * 2 + 1] = b;
+      v[u][e] = k < n ? vi[k] : cmk<Tb>(0, 0);
     }
   }
+}
+
+// Sums of 2 kIV = 8 values over the 64 lanes of a wave by recursive halving: at each
+// of the first three steps a lane keeps half of its values and adds the partner's
+// copy of them, so value q = 4 b5 + 2 b4 + b3 (b = lane bits) ends in the lanes whose
+// bits 5..3 spell q; three more exchanges finish the sum.  10 exchanges instead of 48.
+__device__ __forceinline__ double wave_sum8(double (&x)[8], int lane) {
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+  double y[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double send = b5 ? x[q] : x[q + 4], keep = b5 ? x[q + 4] : x[q];
+    y[q] = keep + __shfl_xor(send, 32, 64);
+  }
+  double z[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const double send = b4 ? y[q] : y[q + 2], keep = b4 ? y[q + 2] : y[q];
+    z[q] = keep + __shfl_xor(send, 16, 64);
+  }
+  double t;
+  {
+    const double send = b3 ? z[0] : z[1], keep = b3 ? z[1] : z[0];
+    t = keep + __shfl_xor(send, 8, 64);
+  }
+  t += __shfl_xor(t, 4, 64);
+  t += __shfl_xor(t, 2, 64);
+  t += __shfl_xor(t, 1, 64);
+  return t;  // the sum of value lane >> 3
+}
+
+// wave partials of conj(V_i) . acc for i in [0, nv), into wsum[(i * 4 + wave) * 2 + {0,1}]
+template <typename Tb>
+__device__ __forceinline__ void wave_dots(const cplx<Tb>* __restrict__ V, const cplx<double> (&acc)[kE], int nv, int r,
+                                          int R, int64_t n, int64_t base, double* wsum) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i0 = 0; i0 < nv; i0 += kIV) {
+    cplx<Tb> v[kIV][kE];
+    load_batch(V, i0, nv, r, R, n, base, v);
+    double x[2 * kIV];
+#pragma unroll
+    for (int u = 0; u < kIV; ++u) {
+      double a = 0, b = 0;
+#pragma unroll
+      for (int e = 0; e < kE; ++e) {
+        const cplx<double> vv = up(v[u][e]);
+        a += vv.re * acc[e].re + vv.im * acc[e].im;
+        b += vv.re * acc[e].im - vv.im * acc[e].re;
+      }
+      x[2 * u] = a;
+      x[2 * u + 1] = b;
+    }
+    const double t = wave_sum8(x, lane);
+    const int q = lane >> 3, i = i0 + (q >> 1);
+    if ((lane & 7) == 0 && i < nv) wsum[(i * 4 + wave) * 2 + (q & 1)] = t;
+  }
+}
+
+// block sums of the wave partials, in wave order, into the chunk slots of part
+__device__ __forceinline__ void store_dots(const double* wsum, double* __restrict__ part, int nv, int r, int c,
+                                           int nch) {
   __syncthreads();
   for (int i = threadIdx.x; i < nv; i += blockDim.x) {
     double a = 0, b = 0;
@@ -101,6 +146,45 @@ __global__ void __launch_bounds__(kBS) k_dots(const cplx<Tb>* __restrict__ V, co
     part[((int64_t(r) * nv + i) * nch + c) * 2] = a;
     part[((int64_t(r) * nv + i) * nch + c) * 2 + 1] = b;
   }
+}
+
+// acc -= sum_{i < nv} V_i coef_i over this thread's elements, in order of i
+template <typename Tb>
+__device__ __forceinline__ void subtract_span(const cplx<Tb>* __restrict__ V, const cplx<double>* __restrict__ cf,
+                                              cplx<double> (&acc)[kE], int nv, int r, int R, int64_t n,
+                                              int64_t base) {
+  for (int i0 = 0; i0 < nv; i0 += kIV) {
+    cplx<Tb> v[kIV][kE];
+    load_batch(V, i0, nv, r, R, n, base, v);
+#pragma unroll
+    for (int u = 0; u < kIV; ++u) {
+      if (i0 + u >= nv) break;
+      const cplx<double> h = cf[i0 + u];
+#pragma unroll
+      for (int e = 0; e < kE; ++e) {
+        const cplx<double> vv = up(v[u][e]);
+        acc[e].re -= vv.re * h.re - vv.im * h.im;
+        acc[e].im -= vv.re * h.im + vv.im * h.re;
+      }
+    }
+  }
+}
+
+// part[((r * nv + i) * nch + c) * 2 + {0,1}] = sum over chunk c of conj(V_i[r]) . w[r], i < nv.
+template <typename Tb>
+__global__ void __launch_bounds__(kBS) k_dots(const cplx<Tb>* __restrict__ V, const cplx<double>* __restrict__ w,
+                                              double* __restrict__ part, int64_t n, int nv, int R) {
+  extern __shared__ double wsum[];  // [nv][4 waves][2]
+  const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
+  const int64_t base = int64_t(c) * kChunk;
+  cplx<double> wl[kE];
+#pragma unroll
+  for (int e = 0; e < kE; ++e) {
+    const int64_t k = base + e * kBS + threadIdx.x;
+    wl[e] = k < n ? w[int64_t(r) * n + k] : cmk<double>(0, 0);
+  }
+  wave_dots(V, wl, nv, r, R, n, base, wsum);
+  store_dots(wsum, part, nv, r, c, nch);
 }
 
 // h[r][i] (+)= sum_c part ; one wave per (r, i), fixed summation order
@@ -137,24 +221,13 @@ __global__ void __launch_bounds__(kBS) k_update(const cplx<Tb>* __restrict__ V, 
   __shared__ double sh[2 * kBS / 64];
   const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
   const int64_t base = int64_t(c) * kChunk;
-  const cplx<double>* cf = coef + int64_t(r) * ldc;
   cplx<double> acc[kE];
 #pragma unroll
   for (int e = 0; e < kE; ++e) {
     const int64_t k = base + e * kBS + threadIdx.x;
     acc[e] = k < n ? w[int64_t(r) * n + k] : cmk<double>(0, 0);
   }
-  for (int i = 0; i < nv; ++i) {
-    const cplx<double> h = cf[i];
-    const cplx<Tb>* vi = V + (int64_t(i) * R + r) * n;
-#pragma unroll
-    for (int e = 0; e < kE; ++e) {
-      const int64_t k = base + e * kBS + threadIdx.x;
-      const cplx<double> v = k < n ? up(vi[k]) : cmk<double>(0, 0);
-      acc[e].re -= v.re * h.re - v.im * h.im;
-      acc[e].im -= v.re * h.im + v.im * h.re;
-    }
-  }
+  subtract_span(V, coef + int64_t(r) * ldc, acc, nv, r, R, n, base);
   double nn = 0, dummy = 0;
 #pragma unroll
   for (int e = 0; e < kE; ++e) {
@@ -180,58 +253,21 @@ __global__ void __launch_bounds__(kBS) k_update_dots(const cplx<Tb>* __restrict_
                                                      double* __restrict__ part, int64_t n, int nv, int R) {
   extern __shared__ double wsum[];  // [nv][4 waves][2]
   const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t base = int64_t(c) * kChunk;
-  const cplx<double>* cf = coef + int64_t(r) * ldc;
   cplx<double> acc[kE];
 #pragma unroll
   for (int e = 0; e < kE; ++e) {
     const int64_t k = base + e * kBS + threadIdx.x;
     acc[e] = k < n ? w[int64_t(r) * n + k] : cmk<double>(0, 0);
   }
-  for (int i = 0; i < nv; ++i) {
-    const cplx<double> h = cf[i];
-    const cplx<Tb>* vi = V + (int64_t(i) * R + r) * n;
-#pragma unroll
-    for (int e = 0; e < kE; ++e) {
-      const int64_t k = base + e * kBS + threadIdx.x;
-      const cplx<double> v = k < n ? up(vi[k]) : cmk<double>(0, 0);
-      acc[e].re -= v.re * h.re - v.im * h.im;
-      acc[e].im -= v.re * h.im + v.im * h.re;
-    }
-  }
+  subtract_span(V, coef + int64_t(r) * ldc, acc, nv, r, R, n, base);
 #pragma unroll
   for (int e = 0; e < kE; ++e) {
     const int64_t k = base + e * kBS + threadIdx.x;
     if (k < n) w[int64_t(r) * n + k] = acc[e];
   }
-  for (int i = 0; i < nv; ++i) {
-    const cplx<Tb>* vi = V + (int64_t(i) * R + r) * n;
-    double a = 0, b = 0;
-#pragma unroll
-    for (int e = 0; e < kE; ++e) {
-      const int64_t k = base + e * kBS + threadIdx.x;
-      const cplx<double> v = k < n ? up(vi[k]) : cmk<double>(0, 0);
-      a += v.re * acc[e].re + v.im * acc[e].im;
-      b += v.re * acc[e].im - v.im * acc[e].re;
-    }
-    a = wave_sum(a);
-    b = wave_sum(b);
-    if (lane == 0) {
-      wsum[(i * 4 + wave) * 2] = a;
-      wsum[(i * 4 + wave) * 2 + 1] = b;
-    }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
-    double a = 0, b = 0;
-    for (int q = 0; q < 4; ++q) {
-      a += wsum[(i * 4 + q) * 2];
-      b += wsum[(i * 4 + q) * 2 + 1];
-    }
-    part[((int64_t(r) * nv + i) * nch + c) * 2] = a;
-    part[((int64_t(r) * nv + i) * nch + c) * 2 + 1] = b;
-  }
+  wave_dots(V, acc, nv, r, R, n, base, wsum);
+  store_dots(wsum, part, nv, r, c, nch);
 }
 
 // chunk partials of ||a - b||^2 (b may be null) and of the difference into out
@@ -284,44 +320,63 @@ __global__ void k_up(const cplx<Tb>* __restrict__ in, cplx<double>* __restrict__
   if (t < n) out[t] = up(in[t]);
 }
 
-// Givens step on column j, one thread per right-hand side.
+// Givens step on column j, one wave per right-hand side.
 //   H[r]: (m+1) x m column-major (ld m+1); h1, h2: the two Gram-Schmidt passes
 //   ([r][m+1]); scal[4r] = ||w||, scal[4r+1] = stop threshold on |g|,
 //   scal[4r+2] = iteration budget of this cycle; jused[r] = 0 while running, set to
 //   j+1 when the residual estimate passes the threshold or the budget runs out,
 //   negative for right-hand sides that are already finished.
-__global__ void k_givens(cplx<double>* H, cplx<double>* cs, cplx<double>* sn, cplx<double>* g,
-                         const cplx<double>* h1, const cplx<double>* h2, const double* scal, int* jused, int m,
-                         int j, int R) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+// The column and the earlier rotations are staged in LDS by the wave; the rotations
+// are applied in order by lane 0, carrying the running entry in registers.
+constexpr int kMaxRestart = 96;
+__global__ void __launch_bounds__(64) k_givens(cplx<double>* H, cplx<double>* cs, cplx<double>* sn, cplx<double>* g,
+                                               const cplx<double>* h1, const cplx<double>* h2, const double* scal,
+                                               int* jused, int m, int j, int R) {
+  __shared__ cplx<double> hc[kMaxRestart + 1], cc[kMaxRestart], ss[kMaxRestart];
+  const int r = blockIdx.x;
   if (r >= R || jused[r] != 0) return;
   cplx<double>* Hc = H + (int64_t(r) * m + j) * (m + 1);
   cplx<double>* c = cs + int64_t(r) * m;
   cplx<double>* s = sn + int64_t(r) * m;
   cplx<double>* gg = g + int64_t(r) * (m + 1);
-  for (int i = 0; i <= j; ++i) Hc[i] = cadd(h1[int64_t(r) * (m + 1) + i], h2[int64_t(r) * (m + 1) + i]);
-  Hc[j + 1] = cmk<double>(scal[4 * r], 0.0);
-  for (int i = 0; i < j; ++i) {
-    const cplx<double> p = Hc[i], q = Hc[i + 1];
-    Hc[i] = cadd(cmulc(p, c[i]), cmulc(q, s[i]));  // conj(c) p + conj(s) q
-    Hc[i + 1] = csub(cmul(c[i], q), cmul(s[i], p));  // -s p + c q
+  for (int i = threadIdx.x; i <= j; i += 64) {
+    hc[i] = cadd(h1[int64_t(r) * (m + 1) + i], h2[int64_t(r) * (m + 1) + i]);
+    if (i < j) {
+      cc[i] = c[i];
+      ss[i] = s[i];
+    }
   }
-  const cplx<double> a = Hc[j], b = Hc[j + 1];
-  const double den = sqrt(a.re * a.re + a.im * a.im + b.re * b.re + b.im * b.im);
-  if (den > 0) {
-    c[j] = cmk<double>(a.re / den, a.im / den);
-    s[j] = cmk<double>(b.re / den, b.im / den);
-  } else {
-    c[j] = cmk<double>(1.0, 0.0);
-    s[j] = cmk<double>(0.0, 0.0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    cplx<double> p = hc[0];
+    for (int i = 0; i < j; ++i) {
+      const cplx<double> q = hc[i + 1], ci = cc[i], si = ss[i];
+      hc[i] = cadd(cmulc(p, ci), cmulc(q, si));  // conj(c) p + conj(s) q
+      p = csub(cmul(ci, q), cmul(si, p));        // -s p + c q
+    }
+    const cplx<double> a = p, b = cmk<double>(scal[4 * r], 0.0);
+    const double den = sqrt(a.re * a.re + a.im * a.im + b.re * b.re + b.im * b.im);
+    cplx<double> cj, sj;
+    if (den > 0) {
+      cj = cmk<double>(a.re / den, a.im / den);
+      sj = cmk<double>(b.re / den, b.im / den);
+    } else {
+      cj = cmk<double>(1.0, 0.0);
+      sj = cmk<double>(0.0, 0.0);
+    }
+    c[j] = cj;
+    s[j] = sj;
+    hc[j] = cmk<double>(den, 0.0);
+    hc[j + 1] = cmk<double>(0.0, 0.0);
+    const cplx<double> gj = gg[j];
+    const cplx<double> gn = cmk<double>(-(sj.re * gj.re - sj.im * gj.im), -(sj.re * gj.im + sj.im * gj.re));
+    gg[j + 1] = gn;
+    gg[j] = cmulc(gj, cj);  // conj(c) g_j
+    const double est = sqrt(gn.re * gn.re + gn.im * gn.im);
+    if (est <= scal[4 * r + 1] || double(j + 1) >= scal[4 * r + 2]) jused[r] = j + 1;
   }
-  Hc[j] = cmk<double>(den, 0.0);
-  Hc[j + 1] = cmk<double>(0.0, 0.0);
-  const cplx<double> gj = gg[j];
-  gg[j + 1] = cmk<double>(-(s[j].re * gj.re - s[j].im * gj.im), -(s[j].re * gj.im + s[j].im * gj.re));
-  gg[j] = cmulc(gj, c[j]);  // conj(c) g_j
-  const double est = sqrt(gg[j + 1].re * gg[j + 1].re + gg[j + 1].im * gg[j + 1].im);
-  if (est <= scal[4 * r + 1] || double(j + 1) >= scal[4 * r + 2]) jused[r] = j + 1;
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j + 1; i += 64) Hc[i] = hc[i];
 }
 
 // y = H^-1 g on the leading k columns (back substitution); k = jused[r] if set,
@@ -398,7 +453,7 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
   const int64_t n = int64_t(op->ne) * op->N;
   const int m = o.restart;
   const int nch = int((n + kChunk - 1) / kChunk);
-  const dim3 gch(nch, R), bs(kBS), g64(nblk(R, 64)), b64(64);
+  const dim3 gch(nch, R), bs(kBS), b64(64);
   cplx<Tb>* V = static_cast<cplx<Tb>*>(K.V);
   GM_LAUNCH(k_residual, gch, bs, 0, s, b, (const cplx<double>*)nullptr, (cplx<double>*)nullptr, K.part, n);
   GM_LAUNCH(k_finish_norm, dim3(R), b64, 0, s, K.part, K.scal + 3, nch, R, 4);
@@ -466,7 +521,7 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
       GM_LAUNCH(k_finish_norm, dim3(R), b64, 0, s, K.part, K.scal, nch, R, 4);
       GM_LAUNCH(k_scale<Tb>, dim3(nblk(n * R, 256)), dim3(256), 0, s, K.w, V + int64_t(j + 1) * R * n, K.scal, 4, n,
                 R);
-      GM_LAUNCH(k_givens, g64, b64, 0, s, K.H, K.cs, K.sn, K.g, K.hcol, K.h2, K.scal, K.active, m, j, R);
+      GM_LAUNCH(k_givens, dim3(R), b64, 0, s, K.H, K.cs, K.sn, K.g, K.hcol, K.h2, K.scal, K.active, m, j, R);
       j_end = j + 1;
       if (j_end % check == 0 || j_end == budget_max) {
         GM_HIP(hipMemcpyAsync(jused.data(), K.active, sizeof(int) * R, hipMemcpyDeviceToHost, s));
@@ -565,7 +620,7 @@ extern "C" int gmres_solve(aim_op* op, const void* b, void* x, int32_t nrhs, con
     set_error("gmres: nrhs must be in [1, max_rhs]");
     return AIM_EINVAL;
   }
-  if (opts->restart < 1 || opts->restart > 96 || opts->max_iters < 0 || !(opts->tol > 0) ||
+  if (opts->restart < 1 || opts->restart > kMaxRestart || opts->max_iters < 0 || !(opts->tol > 0) ||
       (opts->precision != AIM_FP64 && opts->precision != AIM_MIXED)) {
     set_error("gmres: bad options (restart in [1,96], max_iters >= 0, tol > 0, precision)");
     return AIM_EINVAL;

@@ -95,6 +95,7 @@ struct aim_op {
   bool m_set = false, d_set = false;
   bool device_ready = false;  // false for ops from aim_build_host
   int64_t d_nnz = 0;
+  int d_max = 0;  // slots per row of the padded D layout
   size_t lds_max = 65536;
   aimm::DeviceMem mem;
   int *sloc = nullptr, *node_ptr = nullptr, *node_ent = nullptr, *node_n = nullptr, *near_ptr = nullptr,
@@ -103,7 +104,7 @@ struct aim_op {
   int *grp_ptr = nullptr, *grp_col = nullptr;
   bool near_mfma = true;
   int interp_tx = 0, interp_ty = 0;  // 0 = automatic  // [n_off][2] lattice offsets of the near-field blocks
-  int *nbr = nullptr, *d_ptr = nullptr, *d_col = nullptr, *rev_x = nullptr, *rev_y = nullptr, *col_list = nullptr;
+  int *nbr = nullptr, *d_colT = nullptr, *rev_x = nullptr, *rev_y = nullptr, *col_list = nullptr;
   aimm::PrecData<double> p64;
   aimm::PrecData<float> p32;
   void* u = nullptr;      // [R][N][n_elem] macromodel output, element-fastest (sized for complex128)
