@@ -162,7 +162,9 @@ typedef struct {
                            products and FP32 basis storage, FP64 dot products,
                            Hessenberg and Givens; FP64 residual at every restart */
   int32_t x0_given;     /* 0: start from x = 0; 1: start from the x passed in */
-  int32_t check_every;  /* iterations between host convergence checks (>= 1) */
+  int32_t check_every;  /* most iterations between host checks of the stop flags
+                           (>= 1); checks come earlier where the residual estimate
+                           predicts convergence.  Results do not depend on it. */
   double tol;           /* relative residual target ||b - A x|| / ||b|| */
 } gmres_opts;
 
@@ -170,7 +172,8 @@ typedef struct {
   int32_t iters;        /* inner iterations */
   int32_t restarts;     /* completed cycles */
   int32_t converged;    /* 1 if the FP64 true relative residual <= tol */
-  int32_t matvecs;      /* products applied to this right-hand side */
+  int32_t matvecs;      /* products applied to this right-hand side (the first
+                           cycle from x = 0 needs none for its residual) */
   double true_relres;   /* final FP64 true relative residual */
 } gmres_stat;
 

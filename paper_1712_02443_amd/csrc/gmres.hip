@@ -187,20 +187,21 @@ __global__ void __launch_bounds__(kBS) k_dots(const cplx<Tb>* __restrict__ V, co
   store_dots(wsum, part, nv, r, c, nch);
 }
 
-// h[r][i] (+)= sum_c part ; one wave per (r, i), fixed summation order
-__global__ void __launch_bounds__(64) k_reduce_dots(const double* __restrict__ part, cplx<double>* h, int nch, int nv,
-                                                    int R, int ldh, int accumulate) {
+// h[r][i] (+)= sum_c part ; one block per (r, i), fixed summation order
+__global__ void __launch_bounds__(kBS) k_reduce_dots(const double* __restrict__ part, cplx<double>* h, int nch, int nv,
+                                                     int R, int ldh, int accumulate) {
+  __shared__ double sh[2 * kBS / 64];
   const int t = blockIdx.x;
   if (t >= nv * R) return;
   const int r = t / nv, i = t - r * nv;
   const double* p = part + int64_t(t) * nch * 2;
   double a = 0, b = 0;
-  for (int c = threadIdx.x; c < nch; c += 64) {
+#pragma unroll 4
+  for (int c = threadIdx.x; c < nch; c += kBS) {
     a += p[2 * c];
     b += p[2 * c + 1];
   }
-  a = wave_sum(a);
-  b = wave_sum(b);
+  block_sum2(a, b, sh);
   if (threadIdx.x == 0) {
     cplx<double>& o = h[int64_t(r) * ldh + i];
     if (accumulate) {
@@ -270,6 +271,123 @@ __global__ void __launch_bounds__(kBS) k_update_dots(const cplx<Tb>* __restrict_
   store_dots(wsum, part, nv, r, c, nch);
 }
 
+// ---- register-resident variants: one element per thread, the thread's values of all
+// nv <= NVB basis vectors loaded at once and kept in registers, so a pass reads each
+// V_i once however many uses it has (update then projections) and all loads of a
+// thread are in flight together.  Chunks are kBS elements.
+
+// An empty asm that claims to modify v: the conversion of a held FP32 value to FP64
+// cannot be hoisted above it, so the span stays in registers at its own width.
+template <typename Tb>
+__device__ __forceinline__ cplx<Tb> keep(cplx<Tb> v) {
+  asm volatile("" : "+v"(v.re), "+v"(v.im));
+  return v;
+}
+
+template <typename Tb, int NVB>
+__device__ __forceinline__ void load_span(const cplx<Tb>* __restrict__ V, int nv, int r, int R, int64_t n, int64_t k,
+                                          cplx<Tb> (&v)[NVB]) {
+#pragma unroll
+  for (int i = 0; i < NVB; ++i) v[i] = (i < nv && k < n) ? V[(int64_t(i) * R + r) * n + k] : cmk<Tb>(0, 0);
+}
+
+// wave partials of conj(v_i) . a for i < nv, into wsum[(i * 4 + wave) * 2 + {0,1}]
+template <typename Tb, int NVB>
+__device__ __forceinline__ void span_dots(const cplx<Tb> (&v)[NVB], cplx<double> a, int nv, double* wsum) {
+  static_assert(NVB % kIV == 0, "span");
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i0 = 0; i0 < NVB; i0 += kIV) {
+    if (i0 < nv) {
+      double x[2 * kIV];
+#pragma unroll
+      for (int u = 0; u < kIV; ++u) {
+        const cplx<double> vv = up(keep(v[i0 + u]));
+        x[2 * u] = vv.re * a.re + vv.im * a.im;
+        x[2 * u + 1] = vv.re * a.im - vv.im * a.re;
+      }
+      const double t = wave_sum8(x, lane);
+      const int q = lane >> 3, i = i0 + (q >> 1);
+      if ((lane & 7) == 0 && i < nv) wsum[(i * 4 + wave) * 2 + (q & 1)] = t;
+    }
+  }
+}
+
+// a -= sum_{i < nv} v_i cf_i, in order of i.  Slots i >= nv hold v_i = 0 and take the
+// last coefficient, so they subtract exact zeros and the loop has no branches.
+template <typename Tb, int NVB>
+__device__ __forceinline__ void span_subtract(const cplx<Tb> (&v)[NVB], const cplx<double>* __restrict__ cf, int nv,
+                                              cplx<double>& a) {
+#pragma unroll
+  for (int i = 0; i < NVB; ++i) {
+    const cplx<double> h = cf[min(i, nv - 1)], vv = up(keep(v[i]));
+    a.re -= vv.re * h.re - vv.im * h.im;
+    a.im -= vv.re * h.im + vv.im * h.re;
+  }
+}
+
+// part <- chunk sums of conj(V_i) . w.  With a low-precision product output wlo, w is
+// first set to its FP64 copy.
+template <typename Tb, int NVB>
+__global__ void __launch_bounds__(kBS) k_dots_span(const cplx<Tb>* __restrict__ V, const cplx<float>* __restrict__ wlo,
+                                                   cplx<double>* __restrict__ w, double* __restrict__ part,
+                                                   int64_t n, int nv, int R) {
+  extern __shared__ double wsum[];
+  const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
+  const int64_t k = int64_t(c) * kBS + threadIdx.x;
+  cplx<Tb> v[NVB];
+  load_span<Tb, NVB>(V, nv, r, R, n, k, v);
+  cplx<double> a = cmk<double>(0, 0);
+  if (k < n) {
+    if (wlo) {
+      a = up(wlo[int64_t(r) * n + k]);
+      w[int64_t(r) * n + k] = a;
+    } else {
+      a = w[int64_t(r) * n + k];
+    }
+  }
+  span_dots<Tb, NVB>(v, a, nv, wsum);
+  store_dots(wsum, part, nv, r, c, nch);
+}
+
+// w <- w - sum_i V_i h1_i, then part <- chunk sums of conj(V_i) . w, one read of V
+template <typename Tb, int NVB>
+__global__ void __launch_bounds__(kBS) k_update_dots_span(const cplx<Tb>* __restrict__ V, cplx<double>* __restrict__ w,
+                                                          const cplx<double>* __restrict__ coef, int ldc,
+                                                          double* __restrict__ part, int64_t n, int nv, int R) {
+  extern __shared__ double wsum[];
+  const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
+  const int64_t k = int64_t(c) * kBS + threadIdx.x;
+  cplx<Tb> v[NVB];
+  load_span<Tb, NVB>(V, nv, r, R, n, k, v);
+  cplx<double> a = k < n ? w[int64_t(r) * n + k] : cmk<double>(0, 0);
+  span_subtract<Tb, NVB>(v, coef + int64_t(r) * ldc, nv, a);
+  if (k < n) w[int64_t(r) * n + k] = a;
+  span_dots<Tb, NVB>(v, a, nv, wsum);
+  store_dots(wsum, part, nv, r, c, nch);
+}
+
+// w <- w - sum_i V_i h2_i and chunk partials of ||w||^2
+template <typename Tb, int NVB>
+__global__ void __launch_bounds__(kBS) k_update_span(const cplx<Tb>* __restrict__ V, cplx<double>* __restrict__ w,
+                                                     const cplx<double>* __restrict__ coef, int ldc,
+                                                     double* __restrict__ part, int64_t n, int nv, int R) {
+  __shared__ double sh[2 * kBS / 64];
+  const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
+  const int64_t k = int64_t(c) * kBS + threadIdx.x;
+  cplx<Tb> v[NVB];
+  load_span<Tb, NVB>(V, nv, r, R, n, k, v);
+  cplx<double> a = k < n ? w[int64_t(r) * n + k] : cmk<double>(0, 0);
+  span_subtract<Tb, NVB>(v, coef + int64_t(r) * ldc, nv, a);
+  double nn = 0, dummy = 0;
+  if (k < n) {
+    w[int64_t(r) * n + k] = a;
+    nn = a.re * a.re + a.im * a.im;
+  }
+  block_sum2(nn, dummy, sh);
+  if (threadIdx.x == 0) part[int64_t(r) * nch + c] = nn;
+}
+
 // chunk partials of ||a - b||^2 (b may be null) and of the difference into out
 __global__ void __launch_bounds__(kBS) k_residual(const cplx<double>* __restrict__ a, const cplx<double>* __restrict__ b,
                                                   cplx<double>* __restrict__ out, double* part, int64_t n) {
@@ -291,14 +409,15 @@ __global__ void __launch_bounds__(kBS) k_residual(const cplx<double>* __restrict
   if (threadIdx.x == 0) part[int64_t(r) * nch + c] = nn;
 }
 
-// out[r] = sqrt(sum_c part[r][c]); one wave per r, fixed summation order
-__global__ void __launch_bounds__(64) k_finish_norm(const double* part, double* out, int nch, int R, int stride) {
+// out[r] = sqrt(sum_c part[r][c]); one block per r, fixed summation order
+__global__ void __launch_bounds__(kBS) k_finish_norm(const double* part, double* out, int nch, int R, int stride) {
+  __shared__ double sh[2 * kBS / 64];
   const int r = blockIdx.x;
   if (r >= R) return;
   double s = 0, dummy = 0;
-  for (int c = threadIdx.x; c < nch; c += 64) s += part[int64_t(r) * nch + c];
-  s = wave_sum(s);
-  (void)dummy;
+#pragma unroll 4
+  for (int c = threadIdx.x; c < nch; c += kBS) s += part[int64_t(r) * nch + c];
+  block_sum2(s, dummy, sh);
   if (threadIdx.x == 0) out[r * stride] = sqrt(s);
 }
 
@@ -431,6 +550,35 @@ __global__ void k_update_x(const cplx<Tb>* __restrict__ V, cplx<double>* __restr
 
 inline unsigned nblk(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
 
+// largest Krylov span the register-resident passes hold (two VGPRs per FP32 value)
+template <typename Tb>
+constexpr int kSpanMax = sizeof(Tb) == sizeof(float) ? 64 : 32;
+
+// pass 0: projections (k_dots_span), 1: update + projections, 2: update + norm
+template <typename Tb, int NVB>
+hipError_t launch_span_n(int pass, const cplx<Tb>* V, const cplx<float>* wlo, cplx<double>* w,
+                         const cplx<double>* coef, int ldc, double* part, int64_t n, int nv, int R, hipStream_t s) {
+  const dim3 g(nblk(n, kBS), R), b(kBS);
+  const size_t lds = sizeof(double) * 8 * nv;
+  if (pass == 0)
+    hipLaunchKernelGGL((k_dots_span<Tb, NVB>), g, b, lds, s, V, wlo, w, part, n, nv, R);
+  else if (pass == 1)
+    hipLaunchKernelGGL((k_update_dots_span<Tb, NVB>), g, b, lds, s, V, w, coef, ldc, part, n, nv, R);
+  else
+    hipLaunchKernelGGL((k_update_span<Tb, NVB>), g, b, 0, s, V, w, coef, ldc, part, n, nv, R);
+  return hipGetLastError();
+}
+
+template <typename Tb>
+hipError_t launch_span(int pass, const cplx<Tb>* V, const cplx<float>* wlo, cplx<double>* w, const cplx<double>* coef,
+                       int ldc, double* part, int64_t n, int nv, int R, hipStream_t s) {
+  if (nv <= 8) return launch_span_n<Tb, 8>(pass, V, wlo, w, coef, ldc, part, n, nv, R, s);
+  if (nv <= 16) return launch_span_n<Tb, 16>(pass, V, wlo, w, coef, ldc, part, n, nv, R, s);
+  if (nv <= 32 || kSpanMax<Tb> <= 32) return launch_span_n<Tb, 32>(pass, V, wlo, w, coef, ldc, part, n, nv, R, s);
+  if constexpr (kSpanMax<Tb> >= 64) return launch_span_n<Tb, 64>(pass, V, wlo, w, coef, ldc, part, n, nv, R, s);
+  return hipErrorInvalidValue;
+}
+
 #define GM_HIP(expr)                                                              \
   do {                                                                            \
     hipError_t _e = (expr);                                                       \
@@ -453,10 +601,11 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
   const int64_t n = int64_t(op->ne) * op->N;
   const int m = o.restart;
   const int nch = int((n + kChunk - 1) / kChunk);
+  const int nchs = int((n + kBS - 1) / kBS);  // chunks of the register-resident passes
   const dim3 gch(nch, R), bs(kBS), b64(64);
   cplx<Tb>* V = static_cast<cplx<Tb>*>(K.V);
   GM_LAUNCH(k_residual, gch, bs, 0, s, b, (const cplx<double>*)nullptr, (cplx<double>*)nullptr, K.part, n);
-  GM_LAUNCH(k_finish_norm, dim3(R), b64, 0, s, K.part, K.scal + 3, nch, R, 4);
+  GM_LAUNCH(k_finish_norm, dim3(R), bs, 0, s, K.part, K.scal + 3, nch, R, 4);
   if (!o.x0_given) GM_HIP(hipMemsetAsync(x, 0, sizeof(cplx<double>) * n * R, s));
   std::vector<double> bnorm(R), relres(R, 1.0), hs(4 * R);
   std::vector<int> active(R, 1), iters(R, 0), restarts(R, 0), matvecs(R, 0), jused(R), jinit(R);
@@ -465,19 +614,27 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
   for (int r = 0; r < R; ++r) bnorm[r] = hs[4 * r + 3];
   std::vector<cplx<double>> g0(size_t(R) * (m + 1));
   const int check = std::max(1, o.check_every);
+  // Host checks of the stop flags: a check costs a round trip, a late one costs the
+  // iterations run past convergence.  Each check extrapolates every running residual
+  // estimate geometrically from the previous check and places the next check where
+  // the slowest is predicted to pass its threshold (at most check_every ahead).
+  std::vector<cplx<double>> gh(size_t(R) * (m + 1));
+  std::vector<double> est_prev(R);
+  std::vector<int> j_prev(R);
+  bool x_zero = !o.x0_given;
   for (;;) {
-    // FP64 true residual r = b - A x
-    int rc = matvec_impl<double>(op, x, K.w, R, AIM_FULL, s);
+    // FP64 true residual r = b - A x (no product while x is still the zero start)
+    int rc = x_zero ? AIM_OK : matvec_impl<double>(op, x, K.w, R, AIM_FULL, s);
     if (rc) return rc;
-    GM_LAUNCH(k_residual, gch, bs, 0, s, b, K.w, K.r, K.part, n);
-    GM_LAUNCH(k_finish_norm, dim3(R), b64, 0, s, K.part, K.scal, nch, R, 4);
+    GM_LAUNCH(k_residual, gch, bs, 0, s, b, x_zero ? (const cplx<double>*)nullptr : K.w, K.r, K.part, n);
+    GM_LAUNCH(k_finish_norm, dim3(R), bs, 0, s, K.part, K.scal, nch, R, 4);
     GM_HIP(hipMemcpyAsync(hs.data(), K.scal, sizeof(double) * 4 * R, hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
     bool any = false;
     int budget_max = 0;
     for (int r = 0; r < R; ++r) {
       if (!active[r]) continue;
-      matvecs[r] += 1;
+      if (!x_zero) matvecs[r] += 1;
       relres[r] = bnorm[r] > 0 ? hs[4 * r] / bnorm[r] : 0.0;
       if (relres[r] <= o.tol || iters[r] >= o.max_iters) {
         active[r] = 0;
@@ -497,9 +654,17 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
     GM_HIP(hipMemcpyAsync(K.active, jinit.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
     GM_HIP(hipMemcpyAsync(K.g, g0.data(), sizeof(cplx<double>) * g0.size(), hipMemcpyHostToDevice, s));
     GM_LAUNCH(k_scale<Tb>, dim3(nblk(n * R, 256)), dim3(256), 0, s, K.r, V, K.scal, 4, n, R);
-    int j_end = 0;
+    x_zero = false;
+    for (int r = 0; r < R; ++r) {
+      est_prev[r] = hs[4 * r];
+      j_prev[r] = 0;
+    }
+    int j_end = 0, next_check = std::min(check, budget_max);
     for (int j = 0; j < budget_max; ++j) {
       const cplx<Tb>* vj = V + int64_t(j) * R * n;
+      const int nv = j + 1;
+      const bool span = nv <= kSpanMax<Tb>;
+      const cplx<float>* wlo = nullptr;
       if (sizeof(Tb) == sizeof(double)) {
         rc = matvec_impl<double>(op, reinterpret_cast<const cplx<double>*>(vj), K.w, R, AIM_FULL, s);
         if (rc) return rc;
@@ -507,29 +672,53 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
         rc = matvec_impl<float>(op, reinterpret_cast<const cplx<float>*>(vj), static_cast<cplx<float>*>(K.ylow), R,
                                 AIM_FULL, s);
         if (rc) return rc;
-        GM_LAUNCH(k_up<float>, dim3(nblk(n * R, 256)), dim3(256), 0, s, static_cast<const cplx<float>*>(K.ylow),
-                  K.w, n * R);
+        wlo = static_cast<const cplx<float>*>(K.ylow);
+        if (!span)
+          GM_LAUNCH(k_up<float>, dim3(nblk(n * R, 256)), dim3(256), 0, s, wlo, K.w, n * R);
       }
-      const int nv = j + 1;
       // classical Gram-Schmidt, twice
       const size_t dots_lds = sizeof(double) * 8 * nv;
-      GM_LAUNCH(k_dots<Tb>, gch, bs, dots_lds, s, V, K.w, K.part, n, nv, R);
-      GM_LAUNCH(k_reduce_dots, dim3(nv * R), b64, 0, s, K.part, K.hcol, nch, nv, R, m + 1, 0);
-      GM_LAUNCH(k_update_dots<Tb>, gch, bs, dots_lds, s, V, K.w, K.hcol, m + 1, K.part, n, nv, R);
-      GM_LAUNCH(k_reduce_dots, dim3(nv * R), b64, 0, s, K.part, K.h2, nch, nv, R, m + 1, 0);
-      GM_LAUNCH(k_update<Tb>, gch, bs, 0, s, V, K.w, K.h2, m + 1, K.part, n, nv, R, 1);
-      GM_LAUNCH(k_finish_norm, dim3(R), b64, 0, s, K.part, K.scal, nch, R, 4);
+      if (span) {
+        GM_HIP(launch_span<Tb>(0, V, wlo, K.w, nullptr, 0, K.part, n, nv, R, s));
+        GM_LAUNCH(k_reduce_dots, dim3(nv * R), bs, 0, s, K.part, K.hcol, nchs, nv, R, m + 1, 0);
+        GM_HIP(launch_span<Tb>(1, V, nullptr, K.w, K.hcol, m + 1, K.part, n, nv, R, s));
+        GM_LAUNCH(k_reduce_dots, dim3(nv * R), bs, 0, s, K.part, K.h2, nchs, nv, R, m + 1, 0);
+        GM_HIP(launch_span<Tb>(2, V, nullptr, K.w, K.h2, m + 1, K.part, n, nv, R, s));
+        GM_LAUNCH(k_finish_norm, dim3(R), bs, 0, s, K.part, K.scal, nchs, R, 4);
+      } else {
+        GM_LAUNCH(k_dots<Tb>, gch, bs, dots_lds, s, V, K.w, K.part, n, nv, R);
+        GM_LAUNCH(k_reduce_dots, dim3(nv * R), bs, 0, s, K.part, K.hcol, nch, nv, R, m + 1, 0);
+        GM_LAUNCH(k_update_dots<Tb>, gch, bs, dots_lds, s, V, K.w, K.hcol, m + 1, K.part, n, nv, R);
+        GM_LAUNCH(k_reduce_dots, dim3(nv * R), bs, 0, s, K.part, K.h2, nch, nv, R, m + 1, 0);
+        GM_LAUNCH(k_update<Tb>, gch, bs, 0, s, V, K.w, K.h2, m + 1, K.part, n, nv, R, 1);
+        GM_LAUNCH(k_finish_norm, dim3(R), bs, 0, s, K.part, K.scal, nch, R, 4);
+      }
       GM_LAUNCH(k_scale<Tb>, dim3(nblk(n * R, 256)), dim3(256), 0, s, K.w, V + int64_t(j + 1) * R * n, K.scal, 4, n,
                 R);
       GM_LAUNCH(k_givens, dim3(R), b64, 0, s, K.H, K.cs, K.sn, K.g, K.hcol, K.h2, K.scal, K.active, m, j, R);
       j_end = j + 1;
-      if (j_end % check == 0 || j_end == budget_max) {
+      if (j_end >= next_check || j_end == budget_max) {
         GM_HIP(hipMemcpyAsync(jused.data(), K.active, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+        GM_HIP(hipMemcpyAsync(gh.data(), K.g, sizeof(cplx<double>) * gh.size(), hipMemcpyDeviceToHost, s));
         GM_HIP(hipStreamSynchronize(s));
         bool all = true;
-        for (int r = 0; r < R; ++r)
-          if (jused[r] == 0) all = false;
+        int ahead = 1;
+        for (int r = 0; r < R; ++r) {
+          if (jused[r] != 0) continue;
+          all = false;
+          const cplx<double> gv = gh[size_t(r) * (m + 1) + j_end];
+          const double est = std::sqrt(gv.re * gv.re + gv.im * gv.im), thr = hs[4 * r + 1];
+          int need = check;
+          if (est > 0 && est < est_prev[r] && thr > 0) {
+            const double rate = std::log(est / est_prev[r]) / double(j_end - j_prev[r]);
+            need = int(std::ceil(std::log(thr / est) / rate));
+          }
+          ahead = std::max(ahead, std::min(std::max(need, 1), check));
+          est_prev[r] = est;
+          j_prev[r] = j_end;
+        }
         if (all) break;
+        next_check = j_end + ahead;
       }
     }
     GM_LAUNCH(k_lsq, dim3(R), b64, sizeof(cplx<double>) * (size_t(m) * (m + 1) + m + 1), s, K.H, K.g, K.h2,
@@ -588,7 +777,8 @@ int ensure_krylov(aim_op* op, int R, int m, int prec) {
   al(reinterpret_cast<void**>(&K.g), sizeof(cplx<double>) * R * (m + 1));
   al(reinterpret_cast<void**>(&K.hcol), sizeof(cplx<double>) * R * (m + 1));
   al(reinterpret_cast<void**>(&K.h2), sizeof(cplx<double>) * R * (m + 1));
-  K.part_len = size_t(R) * (m + 1) * nch * 2;
+  const int nchs = int((n + kBS - 1) / kBS);
+  K.part_len = size_t(R) * (m + 1) * std::max(nch, nchs) * 2;
   al(reinterpret_cast<void**>(&K.part), sizeof(double) * K.part_len);
   al(reinterpret_cast<void**>(&K.scal), sizeof(double) * 4 * R);
   al(reinterpret_cast<void**>(&K.active), sizeof(int) * R);
