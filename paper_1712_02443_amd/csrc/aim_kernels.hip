@@ -295,13 +295,13 @@ __global__ void __launch_bounds__(256) k_near(const cplx<T>* __restrict__ uT, cp
   __syncthreads();
   for (int idx = threadIdx.x; idx < 64 * kNearRows; idx += 256) {
     const int mm = idx / kNearRows, nn = idx - mm * kNearRows;
-    if (m0 + mm < a.ne && n0 + nn < a.N) nf[(int64_t(r) * a.ne + m0 + mm) * a.N + n0 + nn] = tile[nn][mm];
+    if (m0 + mm < a.ne && n0 + nn < a.N) nf[(int64_t(r) * a.ne + m0 + mm) * a.ld_nf + a.slot_of[n0 + nn]] = tile[nn][mm];
   }
 }
 
 // ---- pre-corrected near field on the matrix cores ---------------------------------
-// Rows are taken in groups of kNearGroup (16); a group's coefficients form a dense
-// 16 x K block over the union of its columns (o, n').  One wave computes 16 rows x 16
+// Rows are clustered into groups of kNearGroup (16); a group's coefficients form a
+// dense 16 x K block over the union of its columns (o, n').  One wave computes 16 rows x 16
 // elements: A (16 x 4) straight from the block, B (4 x 16) = u of the 16 elements'
 // neighbours at offset o, column n' (element-fastest, so each k reads 16 consecutive
 // values).  Four real MFMAs per complex step.
@@ -330,12 +330,12 @@ __device__ __forceinline__ int mfma16_row(int lane, int r) {
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_near_mfma(const cplx<T>* __restrict__ uT, cplx<T>* __restrict__ nf,
-                                                   NearArgs a, const int* __restrict__ grp_ptr,
-                                                   const int* __restrict__ grp_col,
-                                                   const cplx<T>* __restrict__ grp_A) {
-  // four waves: two element halves (16 elements each) x two halves of the union columns
+                                                   NearArgs a, const cplx<T>* __restrict__ grp_A) {
+  // four waves: two element halves (16 elements each) x two halves of the union columns;
+  // the group's column list is staged in LDS so the operand gathers wait on LDS only
   using M = NearMfma<T>;
   __shared__ cplx<T> tile[2][kNearGroupDev][33];
+  extern __shared__ int cols_s[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int eh = wave & 1, kh = wave >> 1;
   const int mblk = blockIdx.x * 32, g = blockIdx.y, r = blockIdx.z;
@@ -344,19 +344,22 @@ __global__ void __launch_bounds__(256) k_near_mfma(const cplx<T>* __restrict__ u
   const bool validb = mb < a.ne;
   const int ix = mb % a.px, iy = mb / a.px;
   const cplx<T>* ur = uT + int64_t(r) * a.N * a.ne;
+  const int g0 = a.grp_ptr[g], ncols = a.grp_ptr[g + 1] - g0;
+  for (int t = threadIdx.x; t < ncols; t += blockDim.x) cols_s[t] = a.grp_col[g0 + t];
+  __syncthreads();
+  const int half = (ncols / 8) * 4;  // first half, a multiple of the K step (4)
+  const int k0 = kh == 0 ? 0 : half, k1 = kh == 0 ? half : ncols;
+  const cplx<T>* Ag = grp_A + int64_t(g0) * kNearGroupDev;
   typename M::acc_t accR = {}, accI = {};
-  const int g0 = grp_ptr[g], g1 = grp_ptr[g + 1];
-  const int half = ((g1 - g0) / 8) * 4;  // first half, a multiple of the K step (4)
-  const int k0 = kh == 0 ? g0 : g0 + half, k1 = kh == 0 ? g0 + half : g1;
   constexpr int P = 4;  // K-steps per batch; the next batch is loaded ahead
   auto fetch = [&](int k, cplx<T>& av, cplx<T>& bv) {
     if (k < k1) {
-      const int col = grp_col[k + kq];
+      const int col = cols_s[k + kq];
       const int np_ = col & 0xFFFF;
       const int jx = ix + ((col >> 16) & 0xFF) - 8, jy = iy + ((col >> 24) & 0xFF) - 8;
       const bool ok = validb && jx >= 0 && jx < a.px && jy >= 0 && jy < a.py;
       bv = ok ? ur[int64_t(np_) * a.ne + jy * a.px + jx] : cmk<T>(0, 0);
-      av = grp_A[int64_t(k + kq) * kNearGroupDev + jcol];
+      av = Ag[int64_t(k + kq) * kNearGroupDev + jcol];
     } else {
       av = cmk<T>(0, 0);
       bv = cmk<T>(0, 0);
@@ -386,11 +389,11 @@ __global__ void __launch_bounds__(256) k_near_mfma(const cplx<T>* __restrict__ u
   for (int rr = 0; rr < 4; ++rr)
     tile[kh][mfma16_row<T>(lane, rr)][eh * 16 + jcol] = cmk<T>(accR[rr], accI[rr]);
   __syncthreads();
-  const int n0 = g * kNearGroupDev;
+  // output in group-slot order: 16 consecutive slots per element
+  const int s0 = g * kNearGroupDev;
   for (int idx = threadIdx.x; idx < 32 * kNearGroupDev; idx += 256) {
     const int mm = idx / kNearGroupDev, nn = idx - mm * kNearGroupDev;
-    if (mblk + mm < a.ne && n0 + nn < a.N)
-      nf[(int64_t(r) * a.ne + mblk + mm) * a.N + n0 + nn] = cadd(tile[0][nn][mm], tile[1][nn][mm]);
+    if (mblk + mm < a.ne) nf[(int64_t(r) * a.ne + mblk + mm) * a.ld_nf + s0 + nn] = cadd(tile[0][nn][mm], tile[1][nn][mm]);
   }
 }
 
@@ -483,7 +486,7 @@ __global__ void __launch_bounds__(256) k_interp(const cplx<T>* __restrict__ Phi,
       if (e < ne_t) {
         const int64_t rowbase = int64_t(r) * rows + int64_t(tm[e]) * a.N;
         cplx<T> out = cmk<T>(T(a.keta) * acc[e].im, -T(a.keta) * acc[e].re);  // -j k eta0 * acc
-        if (MODE != 2) out = cadd(out, nf[rowbase + n]);
+        if (MODE != 2) out = cadd(out, nf[(int64_t(r) * a.ne + tm[e]) * a.ld_nf + a.slot_of[n]]);
         if (MODE == 0) {
           // D row n: slot-major padded layout, so every slot's loads are independent
           const cplx<T>* xe = xs + e * a.N;
@@ -774,7 +777,7 @@ hipError_t launch_near(const cplx<T>* uT, cplx<T>* nf, const NearArgs& a, const 
     // element blocks fastest, so consecutive workgroups (spread over the XCDs) share
     // the rows of u they read
     const dim3 g((a.ne + 31) / 32, (a.N + kNearGroupDev - 1) / kNearGroupDev, a.R);
-    hipLaunchKernelGGL(k_near_mfma<T>, g, dim3(256), 0, s, uT, nf, a, a.grp_ptr, a.grp_col,
+    hipLaunchKernelGGL(k_near_mfma<T>, g, dim3(256), sizeof(int) * size_t(a.grp_max_cols), s, uT, nf, a,
                        reinterpret_cast<const cplx<T>*>(a.grp_A));
   } else {
     const dim3 g((a.N + kNearRows - 1) / kNearRows, (a.ne + 63) / 64, a.R);

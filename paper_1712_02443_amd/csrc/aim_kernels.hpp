@@ -41,7 +41,11 @@ struct NearArgs {
   const int* near_col;
   const int* grp_ptr;  // row-group tables (matrix-core path); grp_A == nullptr selects the CSR path
   const int* grp_col;
+  const int* grp_row;  // [groups][kNearGroupDev] row of each group slot, -1 for none
+  const int* slot_of;  // [N] group slot of each row
   const void* grp_A;
+  int grp_max_cols;    // largest column count of a group (LDS staging of its columns)
+  int ld_nf;           // slots per element of the output (groups x kNearGroupDev)
 };
 
 struct InterpArgs {
@@ -54,6 +58,9 @@ struct InterpArgs {
   // s * N + n (padding: column n, value 0)
   const int* d_colT;
   int dmax;
+  // near-field input, slot-ordered: row n of element m at m * ld_nf + slot_of[n]
+  const int* slot_of;
+  int ld_nf;
 };
 
 inline size_t interp_lds_bytes(const InterpArgs& a, size_t elem) {

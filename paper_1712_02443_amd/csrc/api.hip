@@ -175,7 +175,11 @@ static NearArgs near_args(aim_op* op, int R) {
   a.offsets = op->offsets_d;
   a.grp_ptr = op->grp_ptr;
   a.grp_col = op->grp_col;
+  a.grp_row = op->grp_row;
+  a.slot_of = op->slot_of;
   a.grp_A = nullptr;
+  a.grp_max_cols = op->st.grp_max_cols;
+  a.ld_nf = int(op->st.grp_row.size());
   a.near_ptr = op->near_ptr;
   a.near_col = op->near_col;
   return a;
@@ -203,6 +207,8 @@ static InterpArgs interp_args(aim_op* op, int R) {
   a.sloc = op->sloc;
   a.d_colT = op->d_colT;
   a.dmax = op->d_max;
+  a.slot_of = op->slot_of;
+  a.ld_nf = int(op->st.grp_row.size());
   // element tile of the interpolation workgroup: the projection weights are loaded
   // once per tile, the tile's box of potentials must fit LDS
   // (one element per workgroup measured fastest on the 32 x 32 array)
@@ -420,7 +426,11 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
     op->offsets_d = upload(op, st.offsets.data(), st.offsets.size());
     op->grp_ptr = upload(op, st.grp_ptr.data(), st.grp_ptr.size());
     op->grp_col = upload(op, st.grp_col.data(), st.grp_col.size());
+    op->grp_row = upload(op, st.grp_row.data(), st.grp_row.size());
+    op->slot_of = upload(op, st.slot_of.data(), st.slot_of.size());
     if (const char* env = std::getenv("AIMM_NEAR_CSR")) op->near_mfma = std::atoi(env) == 0;
+    // the matrix-core kernel stages a group's columns in LDS
+    if (size_t(st.grp_max_cols) * sizeof(int) > 32768) op->near_mfma = false;
     if (const char* env = std::getenv("AIMM_INTERP_TILE")) std::sscanf(env, "%dx%d", &op->interp_tx, &op->interp_ty);
     // macromodel column lists, r-major within each kind
     op->type_count.assign(a.n_types, 0);
@@ -463,7 +473,7 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
     // workspaces, sized for complex128
     const size_t n_unk = size_t(op->ne) * op->N * a.max_rhs;
     op->u = op->mem.alloc<cplx<double>>(n_unk);
-    op->nf = op->mem.alloc<cplx<double>>(n_unk);
+    op->nf = op->mem.alloc<cplx<double>>(size_t(op->ne) * st.grp_row.size() * a.max_rhs);
     op->grid = op->mem.alloc<cplx<double>>(size_t(a.max_rhs) * 4 * st.nx * st.ny * st.nz);
     op->S = op->mem.alloc<cplx<double>>(size_t(a.max_rhs) * 4 * st.nx * op->Ly * st.nz);
   } catch (const std::bad_alloc&) {
@@ -783,6 +793,7 @@ size_t aim_footprint_bytes(const aim_surface* surface, const aim_array* array, i
   const size_t n = ne * N;
   size_t b = 0;
   b += n * R * 16;                                   // u
+  b += (N + 15) / 16 * 16 * ne * R * 16;             // near-field output (group-slot order)
   b += R * 4 * nx * ny * ez * 16;                    // grid
   b += R * 4 * nx * Ly * ez * 16;                    // spectrum pass
   b += (Lx / 2 + 1) * (Ly / 2 + 1) * ez * 24;        // kernel spectrum, both precisions
@@ -791,6 +802,8 @@ size_t aim_footprint_bytes(const aim_surface* surface, const aim_array* array, i
   const size_t vec = precision == AIM_FP64 ? 16 : 8;
   b += size_t(restart + 1) * size_t(nrhs) * n * vec;  // Krylov basis
   b += size_t(nrhs) * n * (16 * 3 + 2 * vec);         // GMRES vectors
+  b += size_t(nrhs) * size_t(restart + 1) * (restart + 1) * 16;  // Gram matrices
+  b += size_t(nrhs) * 2 * size_t(restart + 1) * (n / 256 + 1) * 16;  // reduction partials
   return b;
 }
 

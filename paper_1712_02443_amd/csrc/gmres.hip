@@ -1,12 +1,13 @@
 // Restarted GMRES on the final system (section V, eq. finalsystem), one Krylov
 // space per right-hand side, all right-hand sides advanced together.
 //
-// Per cycle: FP64 true residual r = b - A x (FP64 product), v_0 = r / ||r||; then
-// for j = 0 .. m-1: w = A v_j, classical Gram-Schmidt applied twice (CGS2) with
-// FP64 sums, v_{j+1} = w / ||w||, Givens rotations on the FP64 Hessenberg column;
-// finally x += V y with y from the triangular least-squares system.  AIM_MIXED runs
-// the products in complex FP32 and stores the basis in complex FP32; all dot
-// products, norms, the Hessenberg matrix, rotations and x stay FP64.
+// Per cycle: FP64 true residual r = b - A x (FP64 product; none from the zero
+// start), v_0 = r / ||r||; then for j = 0 .. m-1: w = A v_j, classical Gram-Schmidt
+// applied twice (CGS2, in the Gram-matrix form described below) with FP64 sums,
+// v_{j+1} = w' / ||w'||, Givens rotations on the FP64 Hessenberg column; finally
+// x += V y with y from the triangular least-squares system.  AIM_MIXED runs the
+// products in complex FP32 and stores the basis in complex FP32; all dot products,
+// norms, the Gram and Hessenberg matrices, rotations and x stay FP64.
 // Reductions are split into fixed chunks summed in a fixed order, and no value
 // mixes right-hand sides, so each solution is independent of the batch it ran in.
 #include <algorithm>
@@ -60,6 +61,17 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
 }
 
 constexpr int kIV = 4;  // basis vectors loaded together (independent loads in flight)
+constexpr int kMaxRestart = 96;
+
+// ---- one Arnoldi step in Gram form ------------------------------------------------
+// The basis is stored unnormalised: u_{j+1} = w - V c holds the orthogonalised
+// product itself and v_i = s_i u_i with s_i = 1 / ||u_i|| (kept in FP64, s_0 = 1).
+// Classical Gram-Schmidt applied twice gives, with p = V^H w and the Gram matrix
+// S = V^H V, the coefficients c = p + V^H (w - V p) = 2 p - S p; so one pass over the
+// basis computes p and the new column of S (the dots of every v_i with v_j, the
+// product's input), a small per-right-hand-side kernel forms c, and one more pass
+// writes u_{j+1} = w - V c and the partial sums of its norm.  Every dot product and
+// norm is summed in FP64 in a fixed order.
 
 // v[u][e] = V_{min(i0+u, nv-1)}[r][base + e kBS + tid] (zero past n)
 template <typename Tb>
@@ -77,82 +89,107 @@ __device__ __forceinline__ void load_batch(const cplx<Tb>* __restrict__ V, int i
   }
 }
 
-// Sums of 2 kIV = 8 values over the 64 lanes of a wave by recursive halving: at each
-// of the first three steps a lane keeps half of its values and adds the partner's
-// copy of them, so value q = 4 b5 + 2 b4 + b3 (b = lane bits) ends in the lanes whose
-// bits 5..3 spell q; three more exchanges finish the sum.  10 exchanges instead of 48.
+// Lane exchanges without the LDS crossbar.  xchg32 / xchg16: the value of the lane
+// whose bit 5 / bit 4 differs (v_permlane32_swap / v_permlane16_swap exchange the
+// upper and lower halves of each 64- / 32-lane group).  mirror16 / mirror8 / qperm:
+// DPP row_mirror (lane l <-> 15 - l in each row of 16), row_half_mirror (l <-> 7 - l
+// in each group of 8) and quad permutations, all on the vector ALU.
+__device__ __forceinline__ double xchg32(double v, int lane) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const bool up_half = lane & 32;
+  return __hiloint2double(up_half ? ph[0] : ph[1], up_half ? pl[0] : pl[1]);
+}
+__device__ __forceinline__ double xchg16(double v, int lane) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const auto pl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto ph = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  const bool odd_row = lane & 16;
+  return __hiloint2double(odd_row ? ph[0] : ph[1], odd_row ? pl[0] : pl[1]);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kRowMirror = 0x140, kHalfMirror = 0x141, kQuadSwap2 = 0x4E, kQuadSwap1 = 0xB1;
+
+// Sums of 8 values over the 64 lanes of a wave by recursive halving: at each of the
+// first three steps a lane keeps half of its values and adds the partner's copy of
+// them (partners differ in bit 5, then 4, then 3), so value q = 4 b5 + 2 b4 + b3 ends
+// in the lanes whose bits 5..3 spell q; three more exchanges within each group of 8
+// lanes finish the sum.  The summation order is fixed.
 __device__ __forceinline__ double wave_sum8(double (&x)[8], int lane) {
   const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
   double y[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const double send = b5 ? x[q] : x[q + 4], keep = b5 ? x[q + 4] : x[q];
-    y[q] = keep + __shfl_xor(send, 32, 64);
+    y[q] = keep + xchg32(send, lane);
   }
   double z[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const double send = b4 ? y[q] : y[q + 2], keep = b4 ? y[q + 2] : y[q];
-    z[q] = keep + __shfl_xor(send, 16, 64);
+    z[q] = keep + xchg16(send, lane);
   }
   double t;
   {
     const double send = b3 ? z[0] : z[1], keep = b3 ? z[1] : z[0];
-    t = keep + __shfl_xor(send, 8, 64);
+    t = keep + dpp<kRowMirror>(send);
   }
-  t += __shfl_xor(t, 4, 64);
-  t += __shfl_xor(t, 2, 64);
-  t += __shfl_xor(t, 1, 64);
+  t += dpp<kHalfMirror>(t);
+  t += dpp<kQuadSwap2>(t);
+  t += dpp<kQuadSwap1>(t);
   return t;  // the sum of value lane >> 3
 }
 
-// wave partials of conj(V_i) . acc for i in [0, nv), into wsum[(i * 4 + wave) * 2 + {0,1}]
-template <typename Tb>
-__device__ __forceinline__ void wave_dots(const cplx<Tb>* __restrict__ V, const cplx<double> (&acc)[kE], int nv, int r,
-                                          int R, int64_t n, int64_t base, double* wsum) {
+// x = thread partials, for basis vectors i0 and i0 + 1, of (re, im) conj(u_i) . a and
+// (re, im) conj(u_i) . b.  Wave sums go to wsum[((kind * nv + i) * 4 + wave) * 2 + part],
+// kind 0 for a, 1 for b.
+__device__ __forceinline__ void store_pair_sums(double (&x)[8], int i0, int nv, double* wsum) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int i0 = 0; i0 < nv; i0 += kIV) {
-    cplx<Tb> v[kIV][kE];
-    load_batch(V, i0, nv, r, R, n, base, v);
-    double x[2 * kIV];
-#pragma unroll
-    for (int u = 0; u < kIV; ++u) {
-      double a = 0, b = 0;
-#pragma unroll
-      for (int e = 0; e < kE; ++e) {
-        const cplx<double> vv = up(v[u][e]);
-        a += vv.re * acc[e].re + vv.im * acc[e].im;
-        b += vv.re * acc[e].im - vv.im * acc[e].re;
-      }
-      x[2 * u] = a;
-      x[2 * u + 1] = b;
-    }
-    const double t = wave_sum8(x, lane);
-    const int q = lane >> 3, i = i0 + (q >> 1);
-    if ((lane & 7) == 0 && i < nv) wsum[(i * 4 + wave) * 2 + (q & 1)] = t;
-  }
+  const double t = wave_sum8(x, lane);
+  const int q = lane >> 3, i = i0 + (q >> 2), kind = (q >> 1) & 1;
+  if ((lane & 7) == 0 && i < nv) wsum[((kind * nv + i) * 4 + wave) * 2 + (q & 1)] = t;
+}
+
+__device__ __forceinline__ void pair_terms(cplx<double> v, cplx<double> a, cplx<double> b, double* x) {
+  x[0] = v.re * a.re + v.im * a.im;
+  x[1] = v.re * a.im - v.im * a.re;
+  x[2] = v.re * b.re + v.im * b.im;
+  x[3] = v.re * b.im - v.im * b.re;
 }
 
 // block sums of the wave partials, in wave order, into the chunk slots of part
-__device__ __forceinline__ void store_dots(const double* wsum, double* __restrict__ part, int nv, int r, int c,
+__device__ __forceinline__ void store_dots(const double* wsum, double* __restrict__ part, int nvals, int r, int c,
                                            int nch) {
   __syncthreads();
-  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+  for (int i = threadIdx.x; i < nvals; i += blockDim.x) {
     double a = 0, b = 0;
     for (int q = 0; q < 4; ++q) {
       a += wsum[(i * 4 + q) * 2];
       b += wsum[(i * 4 + q) * 2 + 1];
     }
-    part[((int64_t(r) * nv + i) * nch + c) * 2] = a;
-    part[((int64_t(r) * nv + i) * nch + c) * 2 + 1] = b;
+    part[((int64_t(r) * nvals + i) * nch + c) * 2] = a;
+    part[((int64_t(r) * nvals + i) * nch + c) * 2 + 1] = b;
   }
 }
 
-// acc -= sum_{i < nv} V_i coef_i over this thread's elements, in order of i
+// the product A v_j = s_j A u_j at element idx, from its FP32 or FP64 copy
+__device__ __forceinline__ cplx<double> product_value(const cplx<float>* __restrict__ wlo,
+                                                      const cplx<double>* __restrict__ w, int64_t idx, double s) {
+  const cplx<double> a = wlo ? up(wlo[idx]) : w[idx];
+  return cmk<double>(a.re * s, a.im * s);
+}
+
+// acc -= sum_{i < nv} u_i coef_i over this thread's elements, in order of i
 template <typename Tb>
-__device__ __forceinline__ void subtract_span(const cplx<Tb>* __restrict__ V, const cplx<double>* __restrict__ cf,
-                                              cplx<double> (&acc)[kE], int nv, int r, int R, int64_t n,
-                                              int64_t base) {
+__device__ __forceinline__ void subtract_batched(const cplx<Tb>* __restrict__ V, const cplx<double>* __restrict__ cf,
+                                                 cplx<double> (&acc)[kE], int nv, int r, int R, int64_t n,
+                                                 int64_t base) {
   for (int i0 = 0; i0 < nv; i0 += kIV) {
     cplx<Tb> v[kIV][kE];
     load_batch(V, i0, nv, r, R, n, base, v);
@@ -170,21 +207,162 @@ __device__ __forceinline__ void subtract_span(const cplx<Tb>* __restrict__ V, co
   }
 }
 
-// part[((r * nv + i) * nch + c) * 2 + {0,1}] = sum over chunk c of conj(V_i[r]) . w[r], i < nv.
+// Projection pass, any span: chunk partials (kChunk elements) of conj(u_i) . A v_j
+// (values 0 .. nv-1) and conj(u_i) . u_j (values nv .. 2nv-1).
 template <typename Tb>
-__global__ void __launch_bounds__(kBS) k_dots(const cplx<Tb>* __restrict__ V, const cplx<double>* __restrict__ w,
-                                              double* __restrict__ part, int64_t n, int nv, int R) {
-  extern __shared__ double wsum[];  // [nv][4 waves][2]
+__global__ void __launch_bounds__(kBS) k_proj(const cplx<Tb>* __restrict__ V, const cplx<float>* __restrict__ wlo,
+                                              const cplx<double>* __restrict__ w, const double* __restrict__ sc,
+                                              int ldsc, double* __restrict__ part, int64_t n, int nv, int R) {
+  extern __shared__ double wsum[];  // [2 nv][4 waves][2]
   const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
   const int64_t base = int64_t(c) * kChunk;
-  cplx<double> wl[kE];
+  const double sj = sc[int64_t(r) * ldsc + nv - 1];
+  const cplx<Tb>* uj = V + (int64_t(nv - 1) * R + r) * n;
+  cplx<double> a[kE], b[kE];
 #pragma unroll
   for (int e = 0; e < kE; ++e) {
     const int64_t k = base + e * kBS + threadIdx.x;
-    wl[e] = k < n ? w[int64_t(r) * n + k] : cmk<double>(0, 0);
+    a[e] = k < n ? product_value(wlo, w, int64_t(r) * n + k, sj) : cmk<double>(0, 0);
+    b[e] = k < n ? up(uj[k]) : cmk<double>(0, 0);
   }
-  wave_dots(V, wl, nv, r, R, n, base, wsum);
-  store_dots(wsum, part, nv, r, c, nch);
+  for (int i0 = 0; i0 < nv; i0 += kIV) {
+    cplx<Tb> v[kIV][kE];
+    load_batch(V, i0, nv, r, R, n, base, v);
+#pragma unroll
+    for (int h = 0; h < kIV; h += 2) {
+      if (i0 + h < nv) {
+        double x[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int e = 0; e < kE; ++e) {
+            double t[4];
+            pair_terms(up(v[h + u][e]), a[e], b[e], t);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[4 * u + q] += t[q];
+          }
+        store_pair_sums(x, i0 + h, nv, wsum);
+      }
+    }
+  }
+  store_dots(wsum, part, 2 * nv, r, c, nch);
+}
+
+// Update pass, any span: u_{j+1} = A v_j - sum_i u_i cr_i, and chunk partials of its
+// squared norm.
+template <typename Tb>
+__global__ void __launch_bounds__(kBS) k_next(const cplx<Tb>* __restrict__ V, const cplx<float>* __restrict__ wlo,
+                                              const cplx<double>* __restrict__ w, const double* __restrict__ sc,
+                                              int ldsc, const cplx<double>* __restrict__ cr, int ldc,
+                                              cplx<Tb>* __restrict__ unext, double* __restrict__ part, int64_t n,
+                                              int nv, int R) {
+  __shared__ double sh[2 * kBS / 64];
+  const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
+  const int64_t base = int64_t(c) * kChunk;
+  const double sj = sc[int64_t(r) * ldsc + nv - 1];
+  cplx<double> acc[kE];
+#pragma unroll
+  for (int e = 0; e < kE; ++e) {
+    const int64_t k = base + e * kBS + threadIdx.x;
+    acc[e] = k < n ? product_value(wlo, w, int64_t(r) * n + k, sj) : cmk<double>(0, 0);
+  }
+  subtract_batched(V, cr + int64_t(r) * ldc, acc, nv, r, R, n, base);
+  double nn = 0, dummy = 0;
+#pragma unroll
+  for (int e = 0; e < kE; ++e) {
+    const int64_t k = base + e * kBS + threadIdx.x;
+    if (k < n) {
+      unext[int64_t(r) * n + k] = cmk<Tb>(Tb(acc[e].re), Tb(acc[e].im));
+      nn += acc[e].re * acc[e].re + acc[e].im * acc[e].im;
+    }
+  }
+  block_sum2(nn, dummy, sh);
+  if (threadIdx.x == 0) part[int64_t(r) * nch + c] = nn;
+}
+
+// ---- register-resident variants: one element per thread, the thread's values of all
+// nv <= NVB basis vectors loaded at once and kept in registers, so every load of a
+// thread is in flight together.  Chunks are kBS elements.
+
+// An empty asm that claims to modify v: the conversion of a held FP32 value to FP64
+// cannot be hoisted above it, so the span stays in registers at its own width.
+template <typename Tb>
+__device__ __forceinline__ cplx<Tb> keep(cplx<Tb> v) {
+  asm volatile("" : "+v"(v.re), "+v"(v.im));
+  return v;
+}
+
+template <typename Tb, int NVB>
+__device__ __forceinline__ void load_span(const cplx<Tb>* __restrict__ V, int nv, int r, int R, int64_t n, int64_t k,
+                                          cplx<Tb> (&v)[NVB]) {
+#pragma unroll
+  for (int i = 0; i < NVB; ++i) v[i] = (i < nv && k < n) ? V[(int64_t(i) * R + r) * n + k] : cmk<Tb>(0, 0);
+}
+
+template <typename Tb, int NVB>
+__global__ void __launch_bounds__(kBS) k_proj_span(const cplx<Tb>* __restrict__ V, const cplx<float>* __restrict__ wlo,
+                                                   const cplx<double>* __restrict__ w, const double* __restrict__ sc,
+                                                   int ldsc, double* __restrict__ part, int64_t n, int nv, int R) {
+  static_assert(NVB % 2 == 0, "span");
+  extern __shared__ double wsum[];  // [2 nv][4 waves][2]
+  const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
+  const int64_t k = int64_t(c) * kBS + threadIdx.x;
+  cplx<Tb> v[NVB];
+  load_span<Tb, NVB>(V, nv, r, R, n, k, v);
+  const double sj = sc[int64_t(r) * ldsc + nv - 1];
+  const cplx<double> a = k < n ? product_value(wlo, w, int64_t(r) * n + k, sj) : cmk<double>(0, 0);
+  // u_j = v[nv - 1], picked without indexing the register array at run time
+  cplx<Tb> ul = v[0];
+#pragma unroll
+  for (int i = 1; i < NVB; ++i)
+    if (i == nv - 1) ul = v[i];
+  const cplx<double> b = up(ul);
+#pragma unroll
+  for (int i0 = 0; i0 < NVB; i0 += 2) {
+    if (i0 < nv) {
+      double x[8];
+      pair_terms(up(keep(v[i0])), a, b, x);
+      pair_terms(up(keep(v[i0 + 1])), a, b, x + 4);
+      store_pair_sums(x, i0, nv, wsum);
+    }
+  }
+  store_dots(wsum, part, 2 * nv, r, c, nch);
+}
+
+// a -= sum_{i < nv} v_i cf_i, in order of i.  Slots i >= nv hold v_i = 0 and take the
+// last coefficient, so they subtract exact zeros and the loop has no branches.
+template <typename Tb, int NVB>
+__device__ __forceinline__ void span_subtract(const cplx<Tb> (&v)[NVB], const cplx<double>* __restrict__ cf, int nv,
+                                              cplx<double>& a) {
+#pragma unroll
+  for (int i = 0; i < NVB; ++i) {
+    const cplx<double> h = cf[min(i, nv - 1)], vv = up(keep(v[i]));
+    a.re -= vv.re * h.re - vv.im * h.im;
+    a.im -= vv.re * h.im + vv.im * h.re;
+  }
+}
+
+template <typename Tb, int NVB>
+__global__ void __launch_bounds__(kBS) k_next_span(const cplx<Tb>* __restrict__ V, const cplx<float>* __restrict__ wlo,
+                                                   const cplx<double>* __restrict__ w, const double* __restrict__ sc,
+                                                   int ldsc, const cplx<double>* __restrict__ cr, int ldc,
+                                                   cplx<Tb>* __restrict__ unext, double* __restrict__ part, int64_t n,
+                                                   int nv, int R) {
+  __shared__ double sh[2 * kBS / 64];
+  const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
+  const int64_t k = int64_t(c) * kBS + threadIdx.x;
+  cplx<Tb> v[NVB];
+  load_span<Tb, NVB>(V, nv, r, R, n, k, v);
+  const double sj = sc[int64_t(r) * ldsc + nv - 1];
+  cplx<double> a = k < n ? product_value(wlo, w, int64_t(r) * n + k, sj) : cmk<double>(0, 0);
+  span_subtract<Tb, NVB>(v, cr + int64_t(r) * ldc, nv, a);
+  double nn = 0, dummy = 0;
+  if (k < n) {
+    unext[int64_t(r) * n + k] = cmk<Tb>(Tb(a.re), Tb(a.im));
+    nn = a.re * a.re + a.im * a.im;
+  }
+  block_sum2(nn, dummy, sh);
+  if (threadIdx.x == 0) part[int64_t(r) * nch + c] = nn;
 }
 
 // h[r][i] (+)= sum_c part ; one block per (r, i), fixed summation order
@@ -214,178 +392,119 @@ __global__ void __launch_bounds__(kBS) k_reduce_dots(const double* __restrict__ 
   }
 }
 
-// w[r] -= sum_{i<nv} V_i[r] * coef[r][i]; optionally chunk partials of ||w||^2
-template <typename Tb>
-__global__ void __launch_bounds__(kBS) k_update(const cplx<Tb>* __restrict__ V, cplx<double>* __restrict__ w,
-                                                const cplx<double>* __restrict__ coef, int ldc, double* part,
-                                                int64_t n, int nv, int R, int with_norm) {
+// Per right-hand side: p_i = s_i pq_i, new Gram column S_ij = s_i s_j pq_{nv+i}
+// (i <= j), c = 2 p - S p.  hcol <- c (the Hessenberg column above the diagonal),
+// cr <- s_i c_i (coefficients of the stored u_i).  S: [R][m+1][m+1] column-major.
+__global__ void __launch_bounds__(kBS) k_gram(const cplx<double>* __restrict__ pq, int ldpq, cplx<double>* S,
+                                              const double* __restrict__ sc, cplx<double>* __restrict__ hcol,
+                                              cplx<double>* __restrict__ cr, int m, int j, int R) {
+  __shared__ cplx<double> ps[kMaxRestart], qs[kMaxRestart];
+  const int r = blockIdx.x;
+  if (r >= R) return;
+  const int nv = j + 1, ld = m + 1;
+  const double* s = sc + int64_t(r) * ld;
+  const double sj = s[j];
+  cplx<double>* Sr = S + int64_t(r) * ld * ld;
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+    const cplx<double> pv = pq[int64_t(r) * ldpq + i], qv = pq[int64_t(r) * ldpq + nv + i];
+    ps[i] = cmk<double>(pv.re * s[i], pv.im * s[i]);
+    qs[i] = cmk<double>(qv.re * s[i] * sj, qv.im * s[i] * sj);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+    Sr[i + int64_t(j) * ld] = qs[i];
+    Sr[j + int64_t(i) * ld] = cmk<double>(qs[i].re, -qs[i].im);
+    // (S p)_i, entries of column / row j taken from qs (written just now)
+    cplx<double> acc = cmk<double>(0, 0);
+    for (int k = 0; k < nv; ++k) {
+      cplx<double> sik;
+      if (k == j)
+        sik = qs[i];
+      else if (i == j)
+        sik = cmk<double>(qs[k].re, -qs[k].im);
+      else
+        sik = Sr[i + int64_t(k) * ld];
+      cfma(acc, sik, ps[k]);
+    }
+    const cplx<double> cv = cmk<double>(2 * ps[i].re - acc.re, 2 * ps[i].im - acc.im);
+    hcol[int64_t(r) * ld + i] = cv;
+    cr[int64_t(r) * ld + i] = cmk<double>(cv.re * s[i], cv.im * s[i]);
+  }
+}
+
+// Per right-hand side, after the update pass: beta = ||u_{j+1}|| from the chunk
+// partials (fixed order), s_{j+1} = 1 / beta, then the Givens step on column j:
+//   H[r]: (m+1) x m column-major (ld m+1); hcol: the column above the diagonal;
+//   scal[4r] <- beta, scal[4r+1] = stop threshold on |g|, scal[4r+2] = iteration
+//   budget of this cycle; jused[r] = 0 while running, set to j+1 when the residual
+//   estimate passes the threshold or the budget runs out, negative for right-hand
+//   sides that are already finished.
+// The rotations are staged in LDS and applied in order by one thread, carrying the
+// running entry in registers.
+__global__ void __launch_bounds__(kBS) k_finish_step(const double* __restrict__ part, int nch, double* sc,
+                                                     double* scal, cplx<double>* H, cplx<double>* cs,
+                                                     cplx<double>* sn, cplx<double>* g,
+                                                     const cplx<double>* __restrict__ hcol, int* jused, int m, int j,
+                                                     int R) {
   __shared__ double sh[2 * kBS / 64];
-  const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
-  const int64_t base = int64_t(c) * kChunk;
-  cplx<double> acc[kE];
-#pragma unroll
-  for (int e = 0; e < kE; ++e) {
-    const int64_t k = base + e * kBS + threadIdx.x;
-    acc[e] = k < n ? w[int64_t(r) * n + k] : cmk<double>(0, 0);
+  __shared__ cplx<double> hc[kMaxRestart + 1], cc[kMaxRestart], ss[kMaxRestart];
+  __shared__ double beta_s;
+  const int r = blockIdx.x;
+  if (r >= R) return;
+  double sum = 0, dummy = 0;
+#pragma unroll 4
+  for (int c = threadIdx.x; c < nch; c += kBS) sum += part[int64_t(r) * nch + c];
+  block_sum2(sum, dummy, sh);
+  if (threadIdx.x == 0) {
+    const double beta = sqrt(sum);
+    sc[int64_t(r) * (m + 1) + j + 1] = beta > 0 ? 1.0 / beta : 0.0;
+    scal[4 * r] = beta;
+    beta_s = beta;
   }
-  subtract_span(V, coef + int64_t(r) * ldc, acc, nv, r, R, n, base);
-  double nn = 0, dummy = 0;
-#pragma unroll
-  for (int e = 0; e < kE; ++e) {
-    const int64_t k = base + e * kBS + threadIdx.x;
-    if (k < n) {
-      w[int64_t(r) * n + k] = acc[e];
-      nn += acc[e].re * acc[e].re + acc[e].im * acc[e].im;
+  __syncthreads();
+  if (jused[r] != 0) return;
+  cplx<double>* Hc = H + (int64_t(r) * m + j) * (m + 1);
+  cplx<double>* c = cs + int64_t(r) * m;
+  cplx<double>* s = sn + int64_t(r) * m;
+  cplx<double>* gg = g + int64_t(r) * (m + 1);
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+    hc[i] = hcol[int64_t(r) * (m + 1) + i];
+    if (i < j) {
+      cc[i] = c[i];
+      ss[i] = s[i];
     }
   }
-  if (with_norm) {
-    block_sum2(nn, dummy, sh);
-    if (threadIdx.x == 0) part[int64_t(r) * nch + c] = nn;
-  }
-}
-
-// First-pass update fused with the second pass's projections:
-//   w <- w - sum_i V_i h1_i,  then part <- chunk sums of conj(V_i) . w  (i < nv).
-// The second read of each V_i chunk follows the first closely and is served by the
-// caches.
-template <typename Tb>
-__global__ void __launch_bounds__(kBS) k_update_dots(const cplx<Tb>* __restrict__ V, cplx<double>* __restrict__ w,
-                                                     const cplx<double>* __restrict__ coef, int ldc,
-                                                     double* __restrict__ part, int64_t n, int nv, int R) {
-  extern __shared__ double wsum[];  // [nv][4 waves][2]
-  const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
-  const int64_t base = int64_t(c) * kChunk;
-  cplx<double> acc[kE];
-#pragma unroll
-  for (int e = 0; e < kE; ++e) {
-    const int64_t k = base + e * kBS + threadIdx.x;
-    acc[e] = k < n ? w[int64_t(r) * n + k] : cmk<double>(0, 0);
-  }
-  subtract_span(V, coef + int64_t(r) * ldc, acc, nv, r, R, n, base);
-#pragma unroll
-  for (int e = 0; e < kE; ++e) {
-    const int64_t k = base + e * kBS + threadIdx.x;
-    if (k < n) w[int64_t(r) * n + k] = acc[e];
-  }
-  wave_dots(V, acc, nv, r, R, n, base, wsum);
-  store_dots(wsum, part, nv, r, c, nch);
-}
-
-// ---- register-resident variants: one element per thread, the thread's values of all
-// nv <= NVB basis vectors loaded at once and kept in registers, so a pass reads each
-// V_i once however many uses it has (update then projections) and all loads of a
-// thread are in flight together.  Chunks are kBS elements.
-
-// An empty asm that claims to modify v: the conversion of a held FP32 value to FP64
-// cannot be hoisted above it, so the span stays in registers at its own width.
-template <typename Tb>
-__device__ __forceinline__ cplx<Tb> keep(cplx<Tb> v) {
-  asm volatile("" : "+v"(v.re), "+v"(v.im));
-  return v;
-}
-
-template <typename Tb, int NVB>
-__device__ __forceinline__ void load_span(const cplx<Tb>* __restrict__ V, int nv, int r, int R, int64_t n, int64_t k,
-                                          cplx<Tb> (&v)[NVB]) {
-#pragma unroll
-  for (int i = 0; i < NVB; ++i) v[i] = (i < nv && k < n) ? V[(int64_t(i) * R + r) * n + k] : cmk<Tb>(0, 0);
-}
-
-// wave partials of conj(v_i) . a for i < nv, into wsum[(i * 4 + wave) * 2 + {0,1}]
-template <typename Tb, int NVB>
-__device__ __forceinline__ void span_dots(const cplx<Tb> (&v)[NVB], cplx<double> a, int nv, double* wsum) {
-  static_assert(NVB % kIV == 0, "span");
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-  for (int i0 = 0; i0 < NVB; i0 += kIV) {
-    if (i0 < nv) {
-      double x[2 * kIV];
-#pragma unroll
-      for (int u = 0; u < kIV; ++u) {
-        const cplx<double> vv = up(keep(v[i0 + u]));
-        x[2 * u] = vv.re * a.re + vv.im * a.im;
-        x[2 * u + 1] = vv.re * a.im - vv.im * a.re;
-      }
-      const double t = wave_sum8(x, lane);
-      const int q = lane >> 3, i = i0 + (q >> 1);
-      if ((lane & 7) == 0 && i < nv) wsum[(i * 4 + wave) * 2 + (q & 1)] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    cplx<double> p = hc[0];
+    for (int i = 0; i < j; ++i) {
+      const cplx<double> q = hc[i + 1], ci = cc[i], si = ss[i];
+      hc[i] = cadd(cmulc(p, ci), cmulc(q, si));  // conj(c) p + conj(s) q
+      p = csub(cmul(ci, q), cmul(si, p));        // -s p + c q
     }
-  }
-}
-
-// a -= sum_{i < nv} v_i cf_i, in order of i.  Slots i >= nv hold v_i = 0 and take the
-// last coefficient, so they subtract exact zeros and the loop has no branches.
-template <typename Tb, int NVB>
-__device__ __forceinline__ void span_subtract(const cplx<Tb> (&v)[NVB], const cplx<double>* __restrict__ cf, int nv,
-                                              cplx<double>& a) {
-#pragma unroll
-  for (int i = 0; i < NVB; ++i) {
-    const cplx<double> h = cf[min(i, nv - 1)], vv = up(keep(v[i]));
-    a.re -= vv.re * h.re - vv.im * h.im;
-    a.im -= vv.re * h.im + vv.im * h.re;
-  }
-}
-
-// part <- chunk sums of conj(V_i) . w.  With a low-precision product output wlo, w is
-// first set to its FP64 copy.
-template <typename Tb, int NVB>
-__global__ void __launch_bounds__(kBS) k_dots_span(const cplx<Tb>* __restrict__ V, const cplx<float>* __restrict__ wlo,
-                                                   cplx<double>* __restrict__ w, double* __restrict__ part,
-                                                   int64_t n, int nv, int R) {
-  extern __shared__ double wsum[];
-  const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
-  const int64_t k = int64_t(c) * kBS + threadIdx.x;
-  cplx<Tb> v[NVB];
-  load_span<Tb, NVB>(V, nv, r, R, n, k, v);
-  cplx<double> a = cmk<double>(0, 0);
-  if (k < n) {
-    if (wlo) {
-      a = up(wlo[int64_t(r) * n + k]);
-      w[int64_t(r) * n + k] = a;
+    const cplx<double> a = p, b = cmk<double>(beta_s, 0.0);
+    const double den = sqrt(a.re * a.re + a.im * a.im + b.re * b.re + b.im * b.im);
+    cplx<double> cj, sj;
+    if (den > 0) {
+      cj = cmk<double>(a.re / den, a.im / den);
+      sj = cmk<double>(b.re / den, b.im / den);
     } else {
-      a = w[int64_t(r) * n + k];
+      cj = cmk<double>(1.0, 0.0);
+      sj = cmk<double>(0.0, 0.0);
     }
+    c[j] = cj;
+    s[j] = sj;
+    hc[j] = cmk<double>(den, 0.0);
+    hc[j + 1] = cmk<double>(0.0, 0.0);
+    const cplx<double> gj = gg[j];
+    const cplx<double> gn = cmk<double>(-(sj.re * gj.re - sj.im * gj.im), -(sj.re * gj.im + sj.im * gj.re));
+    gg[j + 1] = gn;
+    gg[j] = cmulc(gj, cj);  // conj(c) g_j
+    const double est = sqrt(gn.re * gn.re + gn.im * gn.im);
+    if (est <= scal[4 * r + 1] || double(j + 1) >= scal[4 * r + 2]) jused[r] = j + 1;
   }
-  span_dots<Tb, NVB>(v, a, nv, wsum);
-  store_dots(wsum, part, nv, r, c, nch);
-}
-
-// w <- w - sum_i V_i h1_i, then part <- chunk sums of conj(V_i) . w, one read of V
-template <typename Tb, int NVB>
-__global__ void __launch_bounds__(kBS) k_update_dots_span(const cplx<Tb>* __restrict__ V, cplx<double>* __restrict__ w,
-                                                          const cplx<double>* __restrict__ coef, int ldc,
-                                                          double* __restrict__ part, int64_t n, int nv, int R) {
-  extern __shared__ double wsum[];
-  const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
-  const int64_t k = int64_t(c) * kBS + threadIdx.x;
-  cplx<Tb> v[NVB];
-  load_span<Tb, NVB>(V, nv, r, R, n, k, v);
-  cplx<double> a = k < n ? w[int64_t(r) * n + k] : cmk<double>(0, 0);
-  span_subtract<Tb, NVB>(v, coef + int64_t(r) * ldc, nv, a);
-  if (k < n) w[int64_t(r) * n + k] = a;
-  span_dots<Tb, NVB>(v, a, nv, wsum);
-  store_dots(wsum, part, nv, r, c, nch);
-}
-
-// w <- w - sum_i V_i h2_i and chunk partials of ||w||^2
-template <typename Tb, int NVB>
-__global__ void __launch_bounds__(kBS) k_update_span(const cplx<Tb>* __restrict__ V, cplx<double>* __restrict__ w,
-                                                     const cplx<double>* __restrict__ coef, int ldc,
-                                                     double* __restrict__ part, int64_t n, int nv, int R) {
-  __shared__ double sh[2 * kBS / 64];
-  const int c = blockIdx.x, r = blockIdx.y, nch = gridDim.x;
-  const int64_t k = int64_t(c) * kBS + threadIdx.x;
-  cplx<Tb> v[NVB];
-  load_span<Tb, NVB>(V, nv, r, R, n, k, v);
-  cplx<double> a = k < n ? w[int64_t(r) * n + k] : cmk<double>(0, 0);
-  span_subtract<Tb, NVB>(v, coef + int64_t(r) * ldc, nv, a);
-  double nn = 0, dummy = 0;
-  if (k < n) {
-    w[int64_t(r) * n + k] = a;
-    nn = a.re * a.re + a.im * a.im;
-  }
-  block_sum2(nn, dummy, sh);
-  if (threadIdx.x == 0) part[int64_t(r) * nch + c] = nn;
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) Hc[i] = hc[i];
 }
 
 // chunk partials of ||a - b||^2 (b may be null) and of the difference into out
@@ -433,71 +552,6 @@ __global__ void k_scale(const cplx<double>* __restrict__ w, cplx<Tb>* __restrict
   v[t] = cmk<Tb>(Tb(w[t].re * s), Tb(w[t].im * s));
 }
 
-template <typename Tb>
-__global__ void k_up(const cplx<Tb>* __restrict__ in, cplx<double>* __restrict__ out, int64_t n) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < n) out[t] = up(in[t]);
-}
-
-// Givens step on column j, one wave per right-hand side.
-//   H[r]: (m+1) x m column-major (ld m+1); h1, h2: the two Gram-Schmidt passes
-//   ([r][m+1]); scal[4r] = ||w||, scal[4r+1] = stop threshold on |g|,
-//   scal[4r+2] = iteration budget of this cycle; jused[r] = 0 while running, set to
-//   j+1 when the residual estimate passes the threshold or the budget runs out,
-//   negative for right-hand sides that are already finished.
-// The column and the earlier rotations are staged in LDS by the wave; the rotations
-// are applied in order by lane 0, carrying the running entry in registers.
-constexpr int kMaxRestart = 96;
-__global__ void __launch_bounds__(64) k_givens(cplx<double>* H, cplx<double>* cs, cplx<double>* sn, cplx<double>* g,
-                                               const cplx<double>* h1, const cplx<double>* h2, const double* scal,
-                                               int* jused, int m, int j, int R) {
-  __shared__ cplx<double> hc[kMaxRestart + 1], cc[kMaxRestart], ss[kMaxRestart];
-  const int r = blockIdx.x;
-  if (r >= R || jused[r] != 0) return;
-  cplx<double>* Hc = H + (int64_t(r) * m + j) * (m + 1);
-  cplx<double>* c = cs + int64_t(r) * m;
-  cplx<double>* s = sn + int64_t(r) * m;
-  cplx<double>* gg = g + int64_t(r) * (m + 1);
-  for (int i = threadIdx.x; i <= j; i += 64) {
-    hc[i] = cadd(h1[int64_t(r) * (m + 1) + i], h2[int64_t(r) * (m + 1) + i]);
-    if (i < j) {
-      cc[i] = c[i];
-      ss[i] = s[i];
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    cplx<double> p = hc[0];
-    for (int i = 0; i < j; ++i) {
-      const cplx<double> q = hc[i + 1], ci = cc[i], si = ss[i];
-      hc[i] = cadd(cmulc(p, ci), cmulc(q, si));  // conj(c) p + conj(s) q
-      p = csub(cmul(ci, q), cmul(si, p));        // -s p + c q
-    }
-    const cplx<double> a = p, b = cmk<double>(scal[4 * r], 0.0);
-    const double den = sqrt(a.re * a.re + a.im * a.im + b.re * b.re + b.im * b.im);
-    cplx<double> cj, sj;
-    if (den > 0) {
-      cj = cmk<double>(a.re / den, a.im / den);
-      sj = cmk<double>(b.re / den, b.im / den);
-    } else {
-      cj = cmk<double>(1.0, 0.0);
-      sj = cmk<double>(0.0, 0.0);
-    }
-    c[j] = cj;
-    s[j] = sj;
-    hc[j] = cmk<double>(den, 0.0);
-    hc[j + 1] = cmk<double>(0.0, 0.0);
-    const cplx<double> gj = gg[j];
-    const cplx<double> gn = cmk<double>(-(sj.re * gj.re - sj.im * gj.im), -(sj.re * gj.im + sj.im * gj.re));
-    gg[j + 1] = gn;
-    gg[j] = cmulc(gj, cj);  // conj(c) g_j
-    const double est = sqrt(gn.re * gn.re + gn.im * gn.im);
-    if (est <= scal[4 * r + 1] || double(j + 1) >= scal[4 * r + 2]) jused[r] = j + 1;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i <= j + 1; i += 64) Hc[i] = hc[i];
-}
-
 // y = H^-1 g on the leading k columns (back substitution); k = jused[r] if set,
 // j_end if still running, 0 for finished right-hand sides.  One wave per right-hand
 // side; the triangle is staged in LDS and each step's sum is a lane reduction.
@@ -534,17 +588,22 @@ __global__ void __launch_bounds__(64) k_lsq(const cplx<double>* H, const cplx<do
   for (int t = threadIdx.x; t <= m; t += 64) y[int64_t(r) * (m + 1) + t] = ys[t];
 }
 
-// x[r] += sum_i V_i[r] y[r][i]  (y is zero beyond the used columns)
+// x[r] += sum_i v_i[r] y[r][i] = sum_i u_i[r] (s_i y_i)  (y is zero beyond the used columns)
 template <typename Tb>
 __global__ void k_update_x(const cplx<Tb>* __restrict__ V, cplx<double>* __restrict__ x,
-                           const cplx<double>* __restrict__ y, int64_t n, int nv, int R, int m) {
+                           const cplx<double>* __restrict__ y, const double* __restrict__ sc, int64_t n, int nv, int R,
+                           int m) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= n * R) return;
   const int r = int(t / n);
   const int64_t k = t - int64_t(r) * n;
   cplx<double> acc = x[t];
   const cplx<double>* yr = y + int64_t(r) * (m + 1);
-  for (int i = 0; i < nv; ++i) cfma(acc, up(V[(int64_t(i) * R + r) * n + k]), yr[i]);
+  const double* sr = sc + int64_t(r) * (m + 1);
+  for (int i = 0; i < nv; ++i) {
+    const cplx<double> yi = cmk<double>(yr[i].re * sr[i], yr[i].im * sr[i]);
+    cfma(acc, up(V[(int64_t(i) * R + r) * n + k]), yi);
+  }
   x[t] = acc;
 }
 
@@ -554,29 +613,41 @@ inline unsigned nblk(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
 template <typename Tb>
 constexpr int kSpanMax = sizeof(Tb) == sizeof(float) ? 64 : 32;
 
-// pass 0: projections (k_dots_span), 1: update + projections, 2: update + norm
+// pass 0: projections, 1: update; register-resident when the span fits
 template <typename Tb, int NVB>
-hipError_t launch_span_n(int pass, const cplx<Tb>* V, const cplx<float>* wlo, cplx<double>* w,
-                         const cplx<double>* coef, int ldc, double* part, int64_t n, int nv, int R, hipStream_t s) {
+void launch_step_n(int pass, const cplx<Tb>* V, const cplx<float>* wlo, const cplx<double>* w, const double* sc,
+                   int ldsc, const cplx<double>* cr, int ldc, cplx<Tb>* unext, double* part, int64_t n, int nv, int R,
+                   hipStream_t s) {
   const dim3 g(nblk(n, kBS), R), b(kBS);
-  const size_t lds = sizeof(double) * 8 * nv;
   if (pass == 0)
-    hipLaunchKernelGGL((k_dots_span<Tb, NVB>), g, b, lds, s, V, wlo, w, part, n, nv, R);
-  else if (pass == 1)
-    hipLaunchKernelGGL((k_update_dots_span<Tb, NVB>), g, b, lds, s, V, w, coef, ldc, part, n, nv, R);
+    hipLaunchKernelGGL((k_proj_span<Tb, NVB>), g, b, sizeof(double) * 16 * nv, s, V, wlo, w, sc, ldsc, part, n, nv,
+                       R);
   else
-    hipLaunchKernelGGL((k_update_span<Tb, NVB>), g, b, 0, s, V, w, coef, ldc, part, n, nv, R);
-  return hipGetLastError();
+    hipLaunchKernelGGL((k_next_span<Tb, NVB>), g, b, 0, s, V, wlo, w, sc, ldsc, cr, ldc, unext, part, n, nv, R);
 }
 
+// returns the number of chunk partials per right-hand side the pass wrote
 template <typename Tb>
-hipError_t launch_span(int pass, const cplx<Tb>* V, const cplx<float>* wlo, cplx<double>* w, const cplx<double>* coef,
-                       int ldc, double* part, int64_t n, int nv, int R, hipStream_t s) {
-  if (nv <= 8) return launch_span_n<Tb, 8>(pass, V, wlo, w, coef, ldc, part, n, nv, R, s);
-  if (nv <= 16) return launch_span_n<Tb, 16>(pass, V, wlo, w, coef, ldc, part, n, nv, R, s);
-  if (nv <= 32 || kSpanMax<Tb> <= 32) return launch_span_n<Tb, 32>(pass, V, wlo, w, coef, ldc, part, n, nv, R, s);
-  if constexpr (kSpanMax<Tb> >= 64) return launch_span_n<Tb, 64>(pass, V, wlo, w, coef, ldc, part, n, nv, R, s);
-  return hipErrorInvalidValue;
+int launch_step(int pass, const cplx<Tb>* V, const cplx<float>* wlo, const cplx<double>* w, const double* sc, int ldsc,
+                const cplx<double>* cr, int ldc, cplx<Tb>* unext, double* part, int64_t n, int nv, int R,
+                hipStream_t s) {
+  if (nv > kSpanMax<Tb>) {
+    const dim3 g(nblk(n, kChunk), R), b(kBS);
+    if (pass == 0)
+      hipLaunchKernelGGL(k_proj<Tb>, g, b, sizeof(double) * 16 * nv, s, V, wlo, w, sc, ldsc, part, n, nv, R);
+    else
+      hipLaunchKernelGGL(k_next<Tb>, g, b, 0, s, V, wlo, w, sc, ldsc, cr, ldc, unext, part, n, nv, R);
+    return int(g.x);
+  }
+  if (nv <= 8)
+    launch_step_n<Tb, 8>(pass, V, wlo, w, sc, ldsc, cr, ldc, unext, part, n, nv, R, s);
+  else if (nv <= 16)
+    launch_step_n<Tb, 16>(pass, V, wlo, w, sc, ldsc, cr, ldc, unext, part, n, nv, R, s);
+  else if (nv <= 32 || kSpanMax<Tb> <= 32)
+    launch_step_n<Tb, 32>(pass, V, wlo, w, sc, ldsc, cr, ldc, unext, part, n, nv, R, s);
+  else if constexpr (kSpanMax<Tb> >= 64)
+    launch_step_n<Tb, 64>(pass, V, wlo, w, sc, ldsc, cr, ldc, unext, part, n, nv, R, s);
+  return int(nblk(n, kBS));
 }
 
 #define GM_HIP(expr)                                                              \
@@ -613,6 +684,8 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
   GM_HIP(hipStreamSynchronize(s));
   for (int r = 0; r < R; ++r) bnorm[r] = hs[4 * r + 3];
   std::vector<cplx<double>> g0(size_t(R) * (m + 1));
+  std::vector<double> ib0(size_t(R) * (m + 1), 0.0);  // s_0 = 1: v_0 is stored normalised
+  for (int r = 0; r < R; ++r) ib0[size_t(r) * (m + 1)] = 1.0;
   const int check = std::max(1, o.check_every);
   // Host checks of the stop flags: a check costs a round trip, a late one costs the
   // iterations run past convergence.  Each check extrapolates every running residual
@@ -653,6 +726,7 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
     GM_HIP(hipMemcpyAsync(K.scal, hs.data(), sizeof(double) * 4 * R, hipMemcpyHostToDevice, s));
     GM_HIP(hipMemcpyAsync(K.active, jinit.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
     GM_HIP(hipMemcpyAsync(K.g, g0.data(), sizeof(cplx<double>) * g0.size(), hipMemcpyHostToDevice, s));
+    GM_HIP(hipMemcpyAsync(K.ib, ib0.data(), sizeof(double) * ib0.size(), hipMemcpyHostToDevice, s));
     GM_LAUNCH(k_scale<Tb>, dim3(nblk(n * R, 256)), dim3(256), 0, s, K.r, V, K.scal, 4, n, R);
     x_zero = false;
     for (int r = 0; r < R; ++r) {
@@ -661,41 +735,28 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
     }
     int j_end = 0, next_check = std::min(check, budget_max);
     for (int j = 0; j < budget_max; ++j) {
-      const cplx<Tb>* vj = V + int64_t(j) * R * n;
+      const cplx<Tb>* uj = V + int64_t(j) * R * n;
+      cplx<Tb>* unext = V + int64_t(j + 1) * R * n;
       const int nv = j + 1;
-      const bool span = nv <= kSpanMax<Tb>;
       const cplx<float>* wlo = nullptr;
       if (sizeof(Tb) == sizeof(double)) {
-        rc = matvec_impl<double>(op, reinterpret_cast<const cplx<double>*>(vj), K.w, R, AIM_FULL, s);
+        rc = matvec_impl<double>(op, reinterpret_cast<const cplx<double>*>(uj), K.w, R, AIM_FULL, s);
         if (rc) return rc;
       } else {
-        rc = matvec_impl<float>(op, reinterpret_cast<const cplx<float>*>(vj), static_cast<cplx<float>*>(K.ylow), R,
+        rc = matvec_impl<float>(op, reinterpret_cast<const cplx<float>*>(uj), static_cast<cplx<float>*>(K.ylow), R,
                                 AIM_FULL, s);
         if (rc) return rc;
         wlo = static_cast<const cplx<float>*>(K.ylow);
-        if (!span)
-          GM_LAUNCH(k_up<float>, dim3(nblk(n * R, 256)), dim3(256), 0, s, wlo, K.w, n * R);
       }
-      // classical Gram-Schmidt, twice
-      const size_t dots_lds = sizeof(double) * 8 * nv;
-      if (span) {
-        GM_HIP(launch_span<Tb>(0, V, wlo, K.w, nullptr, 0, K.part, n, nv, R, s));
-        GM_LAUNCH(k_reduce_dots, dim3(nv * R), bs, 0, s, K.part, K.hcol, nchs, nv, R, m + 1, 0);
-        GM_HIP(launch_span<Tb>(1, V, nullptr, K.w, K.hcol, m + 1, K.part, n, nv, R, s));
-        GM_LAUNCH(k_reduce_dots, dim3(nv * R), bs, 0, s, K.part, K.h2, nchs, nv, R, m + 1, 0);
-        GM_HIP(launch_span<Tb>(2, V, nullptr, K.w, K.h2, m + 1, K.part, n, nv, R, s));
-        GM_LAUNCH(k_finish_norm, dim3(R), bs, 0, s, K.part, K.scal, nchs, R, 4);
-      } else {
-        GM_LAUNCH(k_dots<Tb>, gch, bs, dots_lds, s, V, K.w, K.part, n, nv, R);
-        GM_LAUNCH(k_reduce_dots, dim3(nv * R), bs, 0, s, K.part, K.hcol, nch, nv, R, m + 1, 0);
-        GM_LAUNCH(k_update_dots<Tb>, gch, bs, dots_lds, s, V, K.w, K.hcol, m + 1, K.part, n, nv, R);
-        GM_LAUNCH(k_reduce_dots, dim3(nv * R), bs, 0, s, K.part, K.h2, nch, nv, R, m + 1, 0);
-        GM_LAUNCH(k_update<Tb>, gch, bs, 0, s, V, K.w, K.h2, m + 1, K.part, n, nv, R, 1);
-        GM_LAUNCH(k_finish_norm, dim3(R), bs, 0, s, K.part, K.scal, nch, R, 4);
-      }
-      GM_LAUNCH(k_scale<Tb>, dim3(nblk(n * R, 256)), dim3(256), 0, s, K.w, V + int64_t(j + 1) * R * n, K.scal, 4, n,
-                R);
-      GM_LAUNCH(k_givens, dim3(R), b64, 0, s, K.H, K.cs, K.sn, K.g, K.hcol, K.h2, K.scal, K.active, m, j, R);
+      // classical Gram-Schmidt twice, in Gram form
+      int np = launch_step<Tb>(0, V, wlo, K.w, K.ib, m + 1, nullptr, 0, nullptr, K.part, n, nv, R, s);
+      GM_HIP(hipGetLastError());
+      GM_LAUNCH(k_reduce_dots, dim3(2 * nv * R), bs, 0, s, K.part, K.pq, np, 2 * nv, R, 2 * (m + 1), 0);
+      GM_LAUNCH(k_gram, dim3(R), bs, 0, s, K.pq, 2 * (m + 1), K.S, K.ib, K.hcol, K.cr, m, j, R);
+      np = launch_step<Tb>(1, V, wlo, K.w, K.ib, m + 1, K.cr, m + 1, unext, K.part, n, nv, R, s);
+      GM_HIP(hipGetLastError());
+      GM_LAUNCH(k_finish_step, dim3(R), bs, 0, s, K.part, np, K.ib, K.scal, K.H, K.cs, K.sn, K.g, K.hcol, K.active, m,
+                j, R);
       j_end = j + 1;
       if (j_end >= next_check || j_end == budget_max) {
         GM_HIP(hipMemcpyAsync(jused.data(), K.active, sizeof(int) * R, hipMemcpyDeviceToHost, s));
@@ -723,7 +784,7 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
     }
     GM_LAUNCH(k_lsq, dim3(R), b64, sizeof(cplx<double>) * (size_t(m) * (m + 1) + m + 1), s, K.H, K.g, K.h2,
               K.active, m, R, j_end);
-    GM_LAUNCH(k_update_x<Tb>, dim3(nblk(n * R, 256)), dim3(256), 0, s, V, x, K.h2, n, j_end, R, m);
+    GM_LAUNCH(k_update_x<Tb>, dim3(nblk(n * R, 256)), dim3(256), 0, s, V, x, K.h2, K.ib, n, j_end, R, m);
     GM_HIP(hipMemcpyAsync(jused.data(), K.active, sizeof(int) * R, hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
     for (int r = 0; r < R; ++r) {
@@ -747,7 +808,8 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
 }
 
 void free_krylov(KrylovWork& K) {
-  void* ps[] = {K.V, K.w, K.wlow, K.ylow, K.r, K.H, K.cs, K.sn, K.g, K.hcol, K.h2, K.part, K.scal, K.active};
+  void* ps[] = {K.V,  K.w,  K.wlow, K.ylow, K.r,    K.H,    K.cs,     K.sn, K.g,
+                K.hcol, K.h2, K.part, K.scal, K.active, K.S, K.ib, K.pq, K.cr};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   K = KrylovWork{};
@@ -777,8 +839,13 @@ int ensure_krylov(aim_op* op, int R, int m, int prec) {
   al(reinterpret_cast<void**>(&K.g), sizeof(cplx<double>) * R * (m + 1));
   al(reinterpret_cast<void**>(&K.hcol), sizeof(cplx<double>) * R * (m + 1));
   al(reinterpret_cast<void**>(&K.h2), sizeof(cplx<double>) * R * (m + 1));
+  al(reinterpret_cast<void**>(&K.S), sizeof(cplx<double>) * R * (m + 1) * (m + 1));
+  al(reinterpret_cast<void**>(&K.ib), sizeof(double) * R * (m + 1));
+  al(reinterpret_cast<void**>(&K.pq), sizeof(cplx<double>) * R * 2 * (m + 1));
+  al(reinterpret_cast<void**>(&K.cr), sizeof(cplx<double>) * R * (m + 1));
   const int nchs = int((n + kBS - 1) / kBS);
-  K.part_len = size_t(R) * (m + 1) * std::max(nch, nchs) * 2;
+  // chunk partials of up to 2 (m + 1) complex values per right-hand side
+  K.part_len = size_t(R) * 2 * (m + 1) * std::max(nch, nchs) * 2;
   al(reinterpret_cast<void**>(&K.part), sizeof(double) * K.part_len);
   al(reinterpret_cast<void**>(&K.scal), sizeof(double) * 4 * R);
   al(reinterpret_cast<void**>(&K.active), sizeof(int) * R);

@@ -70,10 +70,14 @@ struct KrylovWork {
   cplx<double>* sn = nullptr;
   cplx<double>* g = nullptr;  // [R][restart+1]
   cplx<double>* hcol = nullptr;  // [R][restart+1] first Gram-Schmidt pass
-  cplx<double>* h2 = nullptr;    // [R][restart+1] second pass; least-squares solution
+  cplx<double>* h2 = nullptr;    // [R][restart+1] least-squares solution
   double* part = nullptr;     // reduction partials
   size_t part_len = 0;
   double* scal = nullptr;     // [R][4] norms / flags
+  cplx<double>* S = nullptr;  // [R][restart+1][restart+1] Gram matrix of the basis
+  double* ib = nullptr;       // [R][restart+1] v_i = ib_i u_i (stored u_i unnormalised)
+  cplx<double>* pq = nullptr; // [R][2 (restart+1)] projections and new Gram column
+  cplx<double>* cr = nullptr; // [R][restart+1] update coefficients of the stored u_i
   int* active = nullptr;      // [R] per-cycle stop column
 };
 
@@ -101,7 +105,7 @@ struct aim_op {
   int *sloc = nullptr, *node_ptr = nullptr, *node_ent = nullptr, *node_n = nullptr, *near_ptr = nullptr,
       *near_col = nullptr;
   int* offsets_d = nullptr;
-  int *grp_ptr = nullptr, *grp_col = nullptr;
+  int *grp_ptr = nullptr, *grp_col = nullptr, *grp_row = nullptr, *slot_of = nullptr;
   bool near_mfma = true;
   int interp_tx = 0, interp_ty = 0;  // 0 = automatic  // [n_off][2] lattice offsets of the near-field blocks
   int *nbr = nullptr, *d_colT = nullptr, *rev_x = nullptr, *rev_y = nullptr, *col_list = nullptr;

@@ -496,16 +496,74 @@ void build_setup(const SurfaceIn& s, const ArrayIn& a, Setup& out) {
     }
     out.near_ptr[n + 1] = int32_t(out.near_col.size());
   }
-  // row groups for the matrix-core near field
+  // Row groups for the matrix-core near field.  Every group's coefficient block is
+  // dense over the union of its rows' columns, so rows are clustered greedily: a
+  // group starts at the unassigned row with the smallest edge midpoint (x, then y,
+  // then z) and repeatedly takes the unassigned row that adds the fewest new columns
+  // (lowest index on ties).
   const int ng = (N + kNearGroup - 1) / kNearGroup;
+  int max_col = 0;
+  for (int32_t c : out.near_col) max_col = std::max(max_col, int(c >> 16) * 65536 + (c & 0xFFFF));
+  std::vector<char> in_union(size_t(max_col) + 1, 0), taken(N, 0);
+  out.grp_row.assign(size_t(ng) * kNearGroup, -1);
+  for (int g = 0; g < ng; ++g) {
+    std::vector<int32_t> ucols;
+    auto add_row = [&](int n, int slot) {
+      taken[n] = 1;
+      out.grp_row[size_t(g) * kNearGroup + slot] = n;
+      for (int e = out.near_ptr[n]; e < out.near_ptr[n + 1]; ++e) {
+        const int32_t c = out.near_col[e];
+        const size_t key = size_t(c >> 16) * 65536 + (c & 0xFFFF);
+        if (!in_union[key]) {
+          in_union[key] = 1;
+          ucols.push_back(c);
+        }
+      }
+    };
+    int seed = -1;
+    for (int n = 0; n < N; ++n) {
+      if (taken[n]) continue;
+      if (seed < 0) {
+        seed = n;
+        continue;
+      }
+      const double* cn = &out.cent[3 * n];
+      const double* cs = &out.cent[3 * seed];
+      if (cn[0] < cs[0] || (cn[0] == cs[0] && (cn[1] < cs[1] || (cn[1] == cs[1] && cn[2] < cs[2])))) seed = n;
+    }
+    if (seed < 0) break;
+    add_row(seed, 0);
+    for (int slot = 1; slot < kNearGroup; ++slot) {
+      int best = -1, best_new = 0;
+      for (int n = 0; n < N; ++n) {
+        if (taken[n]) continue;
+        int added = 0;
+        for (int e = out.near_ptr[n]; e < out.near_ptr[n + 1]; ++e) {
+          const int32_t c = out.near_col[e];
+          added += !in_union[size_t(c >> 16) * 65536 + (c & 0xFFFF)];
+        }
+        if (best < 0 || added < best_new) {
+          best = n;
+          best_new = added;
+        }
+      }
+      if (best < 0) break;
+      add_row(best, slot);
+    }
+    for (int32_t c : ucols) in_union[size_t(c >> 16) * 65536 + (c & 0xFFFF)] = 0;
+  }
+  out.slot_of.assign(N, -1);
+  for (int t = 0; t < ng * kNearGroup; ++t)
+    if (out.grp_row[t] >= 0) out.slot_of[out.grp_row[t]] = t;
   out.grp_ptr.assign(ng + 1, 0);
   out.grp_col.clear();
   out.grp_A.clear();
+  out.grp_max_cols = 0;
   for (int g = 0; g < ng; ++g) {
     std::map<int32_t, int> col_index;
     for (int i = 0; i < kNearGroup; ++i) {
-      const int n = g * kNearGroup + i;
-      if (n >= N) break;
+      const int n = out.grp_row[size_t(g) * kNearGroup + i];
+      if (n < 0) continue;
       for (int e = out.near_ptr[n]; e < out.near_ptr[n + 1]; ++e) col_index.emplace(out.near_col[e], 0);
     }
     int k = 0;
@@ -523,12 +581,13 @@ void build_setup(const SurfaceIn& s, const ArrayIn& a, Setup& out) {
                                                                            : dev_col(col_index.begin()->first));
     out.grp_A.resize(out.grp_col.size() * kNearGroup, cd(0.0));
     for (int i = 0; i < kNearGroup; ++i) {
-      const int n = g * kNearGroup + i;
-      if (n >= N) break;
+      const int n = out.grp_row[size_t(g) * kNearGroup + i];
+      if (n < 0) continue;
       for (int e = out.near_ptr[n]; e < out.near_ptr[n + 1]; ++e)
         out.grp_A[(base + col_index[out.near_col[e]]) * kNearGroup + i] = out.near_val[e];
     }
     out.grp_ptr[g + 1] = int32_t(out.grp_col.size());
+    out.grp_max_cols = std::max(out.grp_max_cols, kpad);
   }
 }
 

@@ -38,12 +38,15 @@ struct Setup {
   std::vector<int32_t> near_ptr;     // [N + 1] CSR rows of the pre-corrected near field
   std::vector<int32_t> near_col;     // packed (o << 16) | n'
   std::vector<cd> near_val;          // pre-corrected values C = G_exact - G_grid
-  // near field regrouped for the matrix cores: rows in groups of kNearGroup, each group
+  // near field regrouped for the matrix cores: rows clustered in groups of kNearGroup, each group
   // with the union of its columns (padded to a multiple of 4) and a dense coefficient
   // block A[k][i] = C[group row i][union column k]
   std::vector<int32_t> grp_ptr;      // [n_groups + 1] offsets into grp_col / grp_A (in columns)
   std::vector<int32_t> grp_col;      // packed n' | (dx + 8) << 16 | (dy + 8) << 24
   std::vector<cd> grp_A;             // [total columns][kNearGroup]
+  std::vector<int32_t> grp_row;      // [n_groups][kNearGroup] row n of each group slot (-1: none)
+  std::vector<int32_t> slot_of;      // [N] group slot of row n (the near-field output is slot-ordered)
+  int grp_max_cols = 0;              // largest padded column count of a group
   std::vector<int32_t> node_ptr;     // [ex*ey*ez + 1] projection gather table by local node
   std::vector<int32_t> node_ent;     // packed n * q3 + p
   std::vector<int32_t> node_n;       // n of the same entries
