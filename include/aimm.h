@@ -97,7 +97,14 @@ typedef struct {
   int64_t near_nnz;            /* pre-corrected near-field entries per element row block */
   int64_t d_nnz;               /* entries of the D block (0 until set) */
   int64_t device_bytes;        /* device memory held by the op */
+  int32_t paths;               /* kernels in use: AIM_PATH_FFT_REGISTER (FFT passes of
+                                  in-register DFTs, else radix stages), AIM_PATH_NEAR_MFMA
+                                  (near field on the matrix cores, else sparse rows);
+                                  0 for host-only ops */
 } aim_info;
+
+#define AIM_PATH_FFT_REGISTER 1
+#define AIM_PATH_NEAR_MFMA 2
 
 /* Build the AIM operator of section V for the array: stencils, projection and
  * interpolation weights, FFT plan and Green's-function spectrum (on the device),

@@ -39,7 +39,8 @@ class AimInfo(ctypes.Structure):
     _fields_ = [("n_rwg", ctypes.c_int32), ("n_elem", ctypes.c_int32), ("n_types", ctypes.c_int32),
                 ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("lx", ctypes.c_int32), ("ly", ctypes.c_int32), ("n_offsets", ctypes.c_int32),
-                ("near_nnz", ctypes.c_int64), ("d_nnz", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+                ("near_nnz", ctypes.c_int64), ("d_nnz", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("paths", ctypes.c_int32)]
 
 
 class GmresOpts(ctypes.Structure):

@@ -7,6 +7,7 @@
 //   spectrum S       : [R][4][nx][Ly][nz]      (y transformed, ky in digit-reversed slots)
 #include "aim_kernels.hpp"
 #include "fft.hpp"
+#include "fft4.hpp"
 
 namespace aimm {
 
@@ -243,6 +244,126 @@ __global__ void __launch_bounds__(256) k_fft_y_inv(const cplx<T>* in, cplx<T>* o
   for (int e = threadIdx.x; e < ny * nz; e += blockDim.x) {
     const int y = e / nz, z = e - y * nz;
     dst[e] = buf[z * ld + y];
+  }
+}
+
+// ---- step (ii) with register DFTs (four-step, natural order) for L = L1 L2 --------
+// Same three passes as above; lines are held at the padded slots of fft4_lines, and
+// spectra are in natural order, so no digit-reversal tables are involved.
+template <typename T, int L1, int L2>
+__global__ void __launch_bounds__(512) k_fft4_y_fwd(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+                                                    int ny_in, int nz, const cplx<T>* __restrict__ twg) {
+  constexpr int L = L1 * L2, LD = f4_ld<L1, L2>();
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* buf = tw + L;
+  const int64_t plane = blockIdx.x;
+  const cplx<T>* src = in + plane * int64_t(ny_in) * nz;
+  for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = twg[i];
+  batched_copy<8, T>(
+      ny_in * nz, [&](int e) { return src[e]; },
+      [&](int e, cplx<T> v) {
+        const int y = e / nz, z = e - y * nz;
+        buf[z * LD + f4_slot<L2>(y)] = v;
+      });
+  for (int e = threadIdx.x; e < (L - ny_in) * nz; e += blockDim.x) {
+    const int z = e / (L - ny_in), y = ny_in + (e - z * (L - ny_in));
+    buf[z * LD + f4_slot<L2>(y)] = cmk<T>(0, 0);
+  }
+  __syncthreads();
+  fft4_lines<T, L1, L2, true>(buf, nz, tw);
+  cplx<T>* dst = out + plane * int64_t(L) * nz;
+  for (int e = threadIdx.x; e < L * nz; e += blockDim.x) {
+    const int y = e / nz, z = e - y * nz;
+    dst[e] = buf[z * LD + f4_slot<L2>(y)];
+  }
+}
+
+template <typename T, int L1, int L2>
+__global__ void __launch_bounds__(512) k_fft4_x(const cplx<T>* in, cplx<T>* out, int nx_in, int Ly, int nz, int B,
+                                                const cplx<T>* __restrict__ twg, const cplx<T>* __restrict__ gt) {
+  constexpr int L = L1 * L2, LD = f4_ld<L1, L2>();
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* buf = tw + L;
+  const int nkb = Ly / B;
+  const int64_t plane = blockIdx.x / nkb;
+  const int kb = blockIdx.x - int(plane) * nkb;
+  const int lines = B * nz;
+  const int64_t row = int64_t(Ly) * nz;  // stride between x rows
+  const cplx<T>* src = in + plane * int64_t(nx_in) * row + int64_t(kb) * lines;
+  cplx<T>* dst = out + plane * int64_t(nx_in) * row + int64_t(kb) * lines;
+  for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = twg[i];
+  batched_copy<8, T>(
+      nx_in * lines,
+      [&](int e) {
+        const int x = e / lines, l = e - x * lines;
+        return src[int64_t(x) * row + l];
+      },
+      [&](int e, cplx<T> v) {
+        const int x = e / lines, l = e - x * lines;
+        buf[l * LD + f4_slot<L2>(x)] = v;
+      });
+  for (int e = threadIdx.x; e < (L - nx_in) * lines; e += blockDim.x) {
+    const int l = e / (L - nx_in), x = nx_in + (e - l * (L - nx_in));
+    buf[l * LD + f4_slot<L2>(x)] = cmk<T>(0, 0);
+  }
+  __syncthreads();
+  fft4_lines<T, L1, L2, true>(buf, lines, tw);
+  const int half_y = Ly / 2 + 1;
+  for (int it = threadIdx.x; it < L * B; it += blockDim.x) {
+    const int b = it / L, k = it - b * L;
+    const int kx = min(k, L - k);
+    int ky = kb * B + b;
+    ky = min(ky, Ly - ky);
+    const cplx<T>* g = gt + (int64_t(kx) * half_y + ky) * nz;
+    cplx<T> gv[kMaxNz], v[kMaxNz];
+    const int slot = f4_slot<L2>(k);
+#pragma unroll
+    for (int z = 0; z < kMaxNz; ++z) {
+      gv[z] = z < nz ? g[z] : cmk<T>(0, 0);
+      v[z] = z < nz ? buf[(b * nz + z) * LD + slot] : cmk<T>(0, 0);
+    }
+#pragma unroll
+    for (int z = 0; z < kMaxNz; ++z) {
+      if (z < nz) {
+        cplx<T> acc = cmk<T>(0, 0);
+#pragma unroll
+        for (int zp = 0; zp < kMaxNz; ++zp) cfma(acc, gv[z > zp ? z - zp : zp - z], v[zp]);
+        buf[(b * nz + z) * LD + slot] = acc;
+      }
+    }
+  }
+  __syncthreads();
+  fft4_lines<T, L1, L2, false>(buf, lines, tw);
+  for (int e = threadIdx.x; e < nx_in * lines; e += blockDim.x) {
+    const int x = e / lines, l = e - x * lines;
+    dst[int64_t(x) * row + l] = buf[l * LD + f4_slot<L2>(x)];
+  }
+}
+
+template <typename T, int L1, int L2>
+__global__ void __launch_bounds__(512) k_fft4_y_inv(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, int ny,
+                                                    int nz, const cplx<T>* __restrict__ twg) {
+  constexpr int L = L1 * L2, LD = f4_ld<L1, L2>();
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* buf = tw + L;
+  const int64_t plane = blockIdx.x;
+  const cplx<T>* src = in + plane * int64_t(L) * nz;
+  for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = twg[i];
+  batched_copy<8, T>(
+      L * nz, [&](int e) { return src[e]; },
+      [&](int e, cplx<T> v) {
+        const int y = e / nz, z = e - y * nz;
+        buf[z * LD + f4_slot<L2>(y)] = v;
+      });
+  __syncthreads();
+  fft4_lines<T, L1, L2, false>(buf, nz, tw);
+  cplx<T>* dst = out + plane * int64_t(ny) * nz;
+  for (int e = threadIdx.x; e < ny * nz; e += blockDim.x) {
+    const int y = e / nz, z = e - y * nz;
+    dst[e] = buf[z * LD + f4_slot<L2>(y)];
   }
 }
 
@@ -747,9 +868,54 @@ hipError_t launch_transpose(const cplx<T>* x, cplx<T>* xT, int R, int ne, int N,
   return hipGetLastError();
 }
 
+// the three passes with register DFTs: (LX1, LX2) along x, (LY1, LY2) along y
+template <typename T, int LX1, int LX2, int LY1, int LY2>
+hipError_t launch_convolve4(const cplx<T>* Q, cplx<T>* Phi, cplx<T>* S, const ConvArgs& a, hipStream_t s,
+                            hipEvent_t* ev) {
+  const int planes = a.R * 4 * a.nx;
+  constexpr int Ly = LY1 * LY2, Lx = LX1 * LX2;
+  auto threads = [](int lines, int l1, int l2) { return unsigned((lines * std::max(l1, l2) + 63) / 64 * 64); };
+  if (threads(a.B * a.nz, LX1, LX2) > 512 || threads(a.nz, LY1, LY2) > 512) return hipErrorInvalidConfiguration;
+  size_t lds = sizeof(cplx<T>) * (size_t(Ly) + size_t(a.nz) * f4_ld<LY1, LY2>());
+  hipLaunchKernelGGL((k_fft4_y_fwd<T, LY1, LY2>), dim3(planes), dim3(threads(a.nz, LY1, LY2)), lds, s, Q, S, a.ny,
+                     a.nz, reinterpret_cast<const cplx<T>*>(a.tw_y));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (ev) (void)hipEventRecord(ev[0], s);
+  const int nkb = Ly / a.B;
+  lds = sizeof(cplx<T>) * (size_t(Lx) + size_t(a.B) * a.nz * f4_ld<LX1, LX2>());
+  hipLaunchKernelGGL((k_fft4_x<T, LX1, LX2>), dim3(a.R * 4 * nkb), dim3(threads(a.B * a.nz, LX1, LX2)), lds, s, S, S,
+                     a.nx, Ly, a.nz, a.B, reinterpret_cast<const cplx<T>*>(a.tw_x),
+                     reinterpret_cast<const cplx<T>*>(a.gt));
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (ev) (void)hipEventRecord(ev[1], s);
+  lds = sizeof(cplx<T>) * (size_t(Ly) + size_t(a.nz) * f4_ld<LY1, LY2>());
+  hipLaunchKernelGGL((k_fft4_y_inv<T, LY1, LY2>), dim3(planes), dim3(threads(a.nz, LY1, LY2)), lds, s, S, Phi, a.ny,
+                     a.nz, reinterpret_cast<const cplx<T>*>(a.tw_y));
+  return hipGetLastError();
+}
+
+template <typename T, int LX1, int LX2>
+hipError_t launch_convolve4_y(const cplx<T>* Q, cplx<T>* Phi, cplx<T>* S, const ConvArgs& a, hipStream_t s,
+                              hipEvent_t* ev) {
+#define AIM_F4(LY1, LY2) \
+  if (a.Py.L == LY1 * LY2) return launch_convolve4<T, LX1, LX2, LY1, LY2>(Q, Phi, S, a, s, ev);
+  AIM_F4_LENGTHS(AIM_F4)
+#undef AIM_F4
+  return hipErrorInvalidValue;
+}
+
 template <typename T>
 hipError_t launch_convolve(const cplx<T>* Q, cplx<T>* Phi, cplx<T>* S, const ConvArgs& a, hipStream_t s,
                            hipEvent_t* ev) {
+  if (a.f4) {
+#define AIM_F4(LX1, LX2) \
+  if (a.Px.L == LX1 * LX2) return launch_convolve4_y<T, LX1, LX2>(Q, Phi, S, a, s, ev);
+    AIM_F4_LENGTHS(AIM_F4)
+#undef AIM_F4
+    return hipErrorInvalidValue;
+  }
   const int planes = a.R * 4 * a.nx;
   size_t lds = sizeof(cplx<T>) * size_t(a.Py.L) * (1 + a.nz);
   hipLaunchKernelGGL(k_fft_y_fwd<T>, dim3(planes), dim3(256), lds, s, Q, S, a.ny, a.nz, a.Py,
@@ -865,12 +1031,29 @@ hipError_t launch_convert(const cplx<Tin>* in, cplx<Tout>* out, int64_t n, hipSt
   return hipGetLastError();
 }
 
+bool fft4_supported(int L) {
+#define AIM_F4(L1, L2) \
+  if (L == L1 * L2) return true;
+  AIM_F4_LENGTHS(AIM_F4)
+#undef AIM_F4
+  return false;
+}
+
 hipError_t configure_lds(size_t bytes) {
   const int b = int(bytes);
   hipError_t e = hipSuccess, t;
 #define AIM_ATTR(f)                                                                   \
   t = hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize, b); \
   if (t != hipSuccess) e = t;
+#define AIM_F4_ATTR(L1, L2)                 \
+  AIM_ATTR((k_fft4_y_fwd<float, L1, L2>))  \
+  AIM_ATTR((k_fft4_y_fwd<double, L1, L2>)) \
+  AIM_ATTR((k_fft4_y_inv<float, L1, L2>))  \
+  AIM_ATTR((k_fft4_y_inv<double, L1, L2>)) \
+  AIM_ATTR((k_fft4_x<float, L1, L2>))      \
+  AIM_ATTR((k_fft4_x<double, L1, L2>))
+  AIM_F4_LENGTHS(AIM_F4_ATTR)
+#undef AIM_F4_ATTR
   AIM_ATTR(k_fft_y_fwd<float>)
   AIM_ATTR(k_fft_y_fwd<double>)
   AIM_ATTR(k_fft_y_inv<float>)

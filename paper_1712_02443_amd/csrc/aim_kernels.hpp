@@ -22,8 +22,13 @@ struct ProjArgs {
   const int* node_n;
 };
 
+// FFT lengths L = L1 L2 with register-DFT (four-step) passes
+#define AIM_F4_LENGTHS(X) X(3, 9) X(5, 8) X(6, 9) X(8, 8) X(10, 20) X(20, 20) X(25, 32)
+bool fft4_supported(int L);
+
 struct ConvArgs {
   int R, nx, ny, nz, B;
+  int f4;  // 1: register-DFT passes (natural-order spectra), 0: radix-stage passes
   FftPlan Px, Py;
   const void* tw_x;
   const void* tw_y;

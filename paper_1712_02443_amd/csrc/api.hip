@@ -132,6 +132,7 @@ static ConvArgs conv_args(aim_op* op, const PrecData<T>& P, int R) {
   a.ny = op->st.ny;
   a.nz = op->st.nz;
   a.B = P.B;
+  a.f4 = op->fft4 ? 1 : 0;
   a.Px = op->Px;
   a.Py = op->Py;
   a.tw_x = P.tw_x;
@@ -429,6 +430,9 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
     op->grp_row = upload(op, st.grp_row.data(), st.grp_row.size());
     op->slot_of = upload(op, st.slot_of.data(), st.slot_of.size());
     if (const char* env = std::getenv("AIMM_NEAR_CSR")) op->near_mfma = std::atoi(env) == 0;
+    // register-DFT FFT passes where both padded lengths have a compiled factorisation
+    op->fft4 = fft4_supported(op->Lx) && fft4_supported(op->Ly);
+    if (const char* env = std::getenv("AIMM_FFT4")) op->fft4 = op->fft4 && std::atoi(env) != 0;
     // the matrix-core kernel stages a group's columns in LDS
     if (size_t(st.grp_max_cols) * sizeof(int) > 32768) op->near_mfma = false;
     if (const char* env = std::getenv("AIMM_INTERP_TILE")) std::sscanf(env, "%dx%d", &op->interp_tx, &op->interp_ty);
@@ -750,6 +754,8 @@ int aim_get_info(const aim_op* op, aim_info* info) {
   info->near_nnz = int64_t(op->st.near_val.size());
   info->d_nnz = op->d_nnz;
   info->device_bytes = int64_t(op->mem.bytes);
+  info->paths = op->device_ready ? ((op->fft4 ? AIM_PATH_FFT_REGISTER : 0) | (op->near_mfma ? AIM_PATH_NEAR_MFMA : 0))
+                                 : 0;
   return AIM_OK;
 }
 

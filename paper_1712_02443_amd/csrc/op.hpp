@@ -107,6 +107,7 @@ struct aim_op {
   int* offsets_d = nullptr;
   int *grp_ptr = nullptr, *grp_col = nullptr, *grp_row = nullptr, *slot_of = nullptr;
   bool near_mfma = true;
+  bool fft4 = false;  // register-DFT FFT passes
   int interp_tx = 0, interp_ty = 0;  // 0 = automatic  // [n_off][2] lattice offsets of the near-field blocks
   int *nbr = nullptr, *d_colT = nullptr, *rev_x = nullptr, *rev_y = nullptr, *col_list = nullptr;
   aimm::PrecData<double> p64;

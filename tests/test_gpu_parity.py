@@ -125,6 +125,29 @@ def test_full_product(torch, case, prec):
     assert rel(Y, ref) < TOL[prec]
 
 
+@pytest.mark.parametrize("case", [CASES[0], CASES[2]])
+def test_radix_stage_fft_path(torch, case, monkeypatch):
+    """The radix-stage FFT passes (used for lengths without a register-DFT
+    factorisation) against the oracle, forced on lengths that have one."""
+    from paper_1712_02443_amd import AimOperator
+    wl, op_fast, o = make_pair(torch, case[0], **case[1])
+    assert op_fast.info()["paths"] & 1, "register-DFT FFT passes expected on these lengths"
+    monkeypatch.setenv("AIMM_FFT4", "0")
+    op = AimOperator.from_workload(wl)
+    op.set_macromodels(wl.macromodels())
+    op.set_dmatrix(*wl.d_matrix())
+    assert not op.info()["paths"] & 1
+    say(f"radix-stage FFT {wl.name}")
+    rng = np.random.default_rng(7)
+    Q = rng.standard_normal((1, 4) + o.grid.shape) + 1j * rng.standard_normal((1, 4) + o.grid.shape)
+    for prec in (0, 1):
+        Phi = to_host(op.convolve(to_dev(torch, Q, prec), precision=prec))[0]
+        assert rel(Phi, aim.convolve_fft(Q[0], o.Gs)) < TOL[prec] * (3 if prec == 1 else 1)
+        X = wl.test_vectors()
+        assert rel(to_host(op.matvec(to_dev(torch, X, prec), precision=prec)), o.matvec(X)) < TOL[prec]
+    op.close()
+
+
 def test_product_is_deterministic_and_batch_invariant(torch):
     wl, op, o = make_pair(torch, 2, px=5, py=3, nrhs=3)
     say("determinism")
