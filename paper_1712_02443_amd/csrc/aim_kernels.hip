@@ -250,10 +250,11 @@ __global__ void __launch_bounds__(256) k_fft_y_inv(const cplx<T>* in, cplx<T>* o
 // ---- step (ii) with register DFTs (four-step, natural order) for L = L1 L2 --------
 // Same three passes as above; lines are held at the padded slots of fft4_lines, and
 // spectra are in natural order, so no digit-reversal tables are involved.
-template <typename T, int L1, int L2>
+template <typename T, int L1, int L2, int NZ>
 __global__ void __launch_bounds__(512) k_fft4_y_fwd(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
-                                                    int ny_in, int nz, const cplx<T>* __restrict__ twg) {
+                                                    int ny_in, int nz_rt, const cplx<T>* __restrict__ twg) {
   constexpr int L = L1 * L2, LD = f4_ld<L1, L2>();
+  const int nz = NZ > 0 ? NZ : nz_rt;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* buf = tw + L;
@@ -279,10 +280,12 @@ __global__ void __launch_bounds__(512) k_fft4_y_fwd(const cplx<T>* __restrict__ 
   }
 }
 
-template <typename T, int L1, int L2>
-__global__ void __launch_bounds__(512) k_fft4_x(const cplx<T>* in, cplx<T>* out, int nx_in, int Ly, int nz, int B,
+template <typename T, int L1, int L2, int NZ>
+__global__ void __launch_bounds__(512) k_fft4_x(const cplx<T>* in, cplx<T>* out, int nx_in, int Ly, int nz_rt, int B,
                                                 const cplx<T>* __restrict__ twg, const cplx<T>* __restrict__ gt) {
   constexpr int L = L1 * L2, LD = f4_ld<L1, L2>();
+  constexpr int ZM = NZ > 0 ? NZ : kMaxNz;  // unrolled z extent
+  const int nz = NZ > 0 ? NZ : nz_rt;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* buf = tw + L;
@@ -317,19 +320,19 @@ __global__ void __launch_bounds__(512) k_fft4_x(const cplx<T>* in, cplx<T>* out,
     int ky = kb * B + b;
     ky = min(ky, Ly - ky);
     const cplx<T>* g = gt + (int64_t(kx) * half_y + ky) * nz;
-    cplx<T> gv[kMaxNz], v[kMaxNz];
+    cplx<T> gv[ZM], v[ZM];
     const int slot = f4_slot<L2>(k);
 #pragma unroll
-    for (int z = 0; z < kMaxNz; ++z) {
+    for (int z = 0; z < ZM; ++z) {
       gv[z] = z < nz ? g[z] : cmk<T>(0, 0);
       v[z] = z < nz ? buf[(b * nz + z) * LD + slot] : cmk<T>(0, 0);
     }
 #pragma unroll
-    for (int z = 0; z < kMaxNz; ++z) {
+    for (int z = 0; z < ZM; ++z) {
       if (z < nz) {
         cplx<T> acc = cmk<T>(0, 0);
 #pragma unroll
-        for (int zp = 0; zp < kMaxNz; ++zp) cfma(acc, gv[z > zp ? z - zp : zp - z], v[zp]);
+        for (int zp = 0; zp < ZM; ++zp) cfma(acc, gv[z > zp ? z - zp : zp - z], v[zp]);
         buf[(b * nz + z) * LD + slot] = acc;
       }
     }
@@ -342,10 +345,11 @@ __global__ void __launch_bounds__(512) k_fft4_x(const cplx<T>* in, cplx<T>* out,
   }
 }
 
-template <typename T, int L1, int L2>
+template <typename T, int L1, int L2, int NZ>
 __global__ void __launch_bounds__(512) k_fft4_y_inv(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, int ny,
-                                                    int nz, const cplx<T>* __restrict__ twg) {
+                                                    int nz_rt, const cplx<T>* __restrict__ twg) {
   constexpr int L = L1 * L2, LD = f4_ld<L1, L2>();
+  const int nz = NZ > 0 ? NZ : nz_rt;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* buf = tw + L;
@@ -868,32 +872,41 @@ hipError_t launch_transpose(const cplx<T>* x, cplx<T>* xT, int R, int ne, int N,
   return hipGetLastError();
 }
 
-// the three passes with register DFTs: (LX1, LX2) along x, (LY1, LY2) along y
-template <typename T, int LX1, int LX2, int LY1, int LY2>
-hipError_t launch_convolve4(const cplx<T>* Q, cplx<T>* Phi, cplx<T>* S, const ConvArgs& a, hipStream_t s,
-                            hipEvent_t* ev) {
+// the three passes with register DFTs: (LX1, LX2) along x, (LY1, LY2) along y; NZ > 0
+// fixes the node count along z at compile time
+template <typename T, int LX1, int LX2, int LY1, int LY2, int NZ>
+hipError_t launch_convolve4_z(const cplx<T>* Q, cplx<T>* Phi, cplx<T>* S, const ConvArgs& a, hipStream_t s,
+                              hipEvent_t* ev) {
   const int planes = a.R * 4 * a.nx;
   constexpr int Ly = LY1 * LY2, Lx = LX1 * LX2;
   auto threads = [](int lines, int l1, int l2) { return unsigned((lines * std::max(l1, l2) + 63) / 64 * 64); };
   if (threads(a.B * a.nz, LX1, LX2) > 512 || threads(a.nz, LY1, LY2) > 512) return hipErrorInvalidConfiguration;
   size_t lds = sizeof(cplx<T>) * (size_t(Ly) + size_t(a.nz) * f4_ld<LY1, LY2>());
-  hipLaunchKernelGGL((k_fft4_y_fwd<T, LY1, LY2>), dim3(planes), dim3(threads(a.nz, LY1, LY2)), lds, s, Q, S, a.ny,
+  hipLaunchKernelGGL((k_fft4_y_fwd<T, LY1, LY2, NZ>), dim3(planes), dim3(threads(a.nz, LY1, LY2)), lds, s, Q, S, a.ny,
                      a.nz, reinterpret_cast<const cplx<T>*>(a.tw_y));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev) (void)hipEventRecord(ev[0], s);
   const int nkb = Ly / a.B;
   lds = sizeof(cplx<T>) * (size_t(Lx) + size_t(a.B) * a.nz * f4_ld<LX1, LX2>());
-  hipLaunchKernelGGL((k_fft4_x<T, LX1, LX2>), dim3(a.R * 4 * nkb), dim3(threads(a.B * a.nz, LX1, LX2)), lds, s, S, S,
+  hipLaunchKernelGGL((k_fft4_x<T, LX1, LX2, NZ>), dim3(a.R * 4 * nkb), dim3(threads(a.B * a.nz, LX1, LX2)), lds, s, S, S,
                      a.nx, Ly, a.nz, a.B, reinterpret_cast<const cplx<T>*>(a.tw_x),
                      reinterpret_cast<const cplx<T>*>(a.gt));
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev) (void)hipEventRecord(ev[1], s);
   lds = sizeof(cplx<T>) * (size_t(Ly) + size_t(a.nz) * f4_ld<LY1, LY2>());
-  hipLaunchKernelGGL((k_fft4_y_inv<T, LY1, LY2>), dim3(planes), dim3(threads(a.nz, LY1, LY2)), lds, s, S, Phi, a.ny,
+  hipLaunchKernelGGL((k_fft4_y_inv<T, LY1, LY2, NZ>), dim3(planes), dim3(threads(a.nz, LY1, LY2)), lds, s, S, Phi, a.ny,
                      a.nz, reinterpret_cast<const cplx<T>*>(a.tw_y));
   return hipGetLastError();
+}
+
+template <typename T, int LX1, int LX2, int LY1, int LY2>
+hipError_t launch_convolve4(const cplx<T>* Q, cplx<T>* Phi, cplx<T>* S, const ConvArgs& a, hipStream_t s,
+                            hipEvent_t* ev) {
+  if (a.nz == 8) return launch_convolve4_z<T, LX1, LX2, LY1, LY2, 8>(Q, Phi, S, a, s, ev);
+  if (a.nz == 9) return launch_convolve4_z<T, LX1, LX2, LY1, LY2, 9>(Q, Phi, S, a, s, ev);
+  return launch_convolve4_z<T, LX1, LX2, LY1, LY2, 0>(Q, Phi, S, a, s, ev);
 }
 
 template <typename T, int LX1, int LX2>
@@ -1045,14 +1058,16 @@ hipError_t configure_lds(size_t bytes) {
 #define AIM_ATTR(f)                                                                   \
   t = hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize, b); \
   if (t != hipSuccess) e = t;
-#define AIM_F4_ATTR(L1, L2)                 \
-  AIM_ATTR((k_fft4_y_fwd<float, L1, L2>))  \
-  AIM_ATTR((k_fft4_y_fwd<double, L1, L2>)) \
-  AIM_ATTR((k_fft4_y_inv<float, L1, L2>))  \
-  AIM_ATTR((k_fft4_y_inv<double, L1, L2>)) \
-  AIM_ATTR((k_fft4_x<float, L1, L2>))      \
-  AIM_ATTR((k_fft4_x<double, L1, L2>))
+#define AIM_F4_ATTR_Z(L1, L2, NZ)                \
+  AIM_ATTR((k_fft4_y_fwd<float, L1, L2, NZ>))   \
+  AIM_ATTR((k_fft4_y_fwd<double, L1, L2, NZ>))  \
+  AIM_ATTR((k_fft4_y_inv<float, L1, L2, NZ>))   \
+  AIM_ATTR((k_fft4_y_inv<double, L1, L2, NZ>))  \
+  AIM_ATTR((k_fft4_x<float, L1, L2, NZ>))       \
+  AIM_ATTR((k_fft4_x<double, L1, L2, NZ>))
+#define AIM_F4_ATTR(L1, L2) AIM_F4_ATTR_Z(L1, L2, 0) AIM_F4_ATTR_Z(L1, L2, 8) AIM_F4_ATTR_Z(L1, L2, 9)
   AIM_F4_LENGTHS(AIM_F4_ATTR)
+#undef AIM_F4_ATTR_Z
 #undef AIM_F4_ATTR
   AIM_ATTR(k_fft_y_fwd<float>)
   AIM_ATTR(k_fft_y_fwd<double>)

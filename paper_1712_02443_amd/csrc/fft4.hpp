@@ -146,7 +146,7 @@ constexpr int f4_ld() {
 // Transform nlines lines at buf + line * f4_ld in place.  tw[t] = exp(-2 pi i t / L)
 // for t < L (LDS).  Needs blockDim.x >= nlines * max(L1, L2); ends with a barrier.
 template <typename T, int L1, int L2, bool FWD>
-__device__ void fft4_lines(cplx<T>* buf, int nlines, const cplx<T>* tw) {
+__device__ __forceinline__ void fft4_lines(cplx<T>* buf, int nlines, const cplx<T>* tw) {
   constexpr int P = L2 + 1, LD = f4_ld<L1, L2>();
   // pass A: one length-L1 DFT per (line, x2), then the twiddles W_L^{x2 k1}
   if (int(threadIdx.x) < nlines * L2) {
