@@ -282,7 +282,8 @@ __global__ void __launch_bounds__(512) k_fft4_y_fwd(const cplx<T>* __restrict__ 
 
 template <typename T, int L1, int L2, int NZ>
 __global__ void __launch_bounds__(512) k_fft4_x(const cplx<T>* in, cplx<T>* out, int nx_in, int Ly, int nz_rt, int B,
-                                                const cplx<T>* __restrict__ twg, const cplx<T>* __restrict__ gt) {
+                                                int n_blocks, const cplx<T>* __restrict__ twg,
+                                                const cplx<T>* __restrict__ gt) {
   constexpr int L = L1 * L2, LD = f4_ld<L1, L2>();
   constexpr int ZM = NZ > 0 ? NZ : kMaxNz;  // unrolled z extent
   const int nz = NZ > 0 ? NZ : nz_rt;
@@ -290,8 +291,14 @@ __global__ void __launch_bounds__(512) k_fft4_x(const cplx<T>* in, cplx<T>* out,
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* buf = tw + L;
   const int nkb = Ly / B;
-  const int64_t plane = blockIdx.x / nkb;
-  const int kb = blockIdx.x - int(plane) * nkb;
+  // Workgroups go to the XCDs round-robin by index; this numbering gives each XCD a
+  // contiguous run of line blocks, so the neighbouring blocks that share cache lines
+  // (a block's rows are only B nz values long) are read through the same L2.
+  const int nblk = int(gridDim.x), per_xcd = (nblk + kXcds - 1) / kXcds;
+  const int lb = int(blockIdx.x % kXcds) * per_xcd + int(blockIdx.x / kXcds);
+  if (lb >= n_blocks) return;
+  const int64_t plane = lb / nkb;
+  const int kb = lb - int(plane) * nkb;
   const int lines = B * nz;
   const int64_t row = int64_t(Ly) * nz;  // stride between x rows
   const cplx<T>* src = in + plane * int64_t(nx_in) * row + int64_t(kb) * lines;
@@ -887,11 +894,11 @@ hipError_t launch_convolve4_z(const cplx<T>* Q, cplx<T>* Phi, cplx<T>* S, const 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev) (void)hipEventRecord(ev[0], s);
-  const int nkb = Ly / a.B;
+  const int nkb = Ly / a.B, nblocks = a.R * 4 * nkb;
   lds = sizeof(cplx<T>) * (size_t(Lx) + size_t(a.B) * a.nz * f4_ld<LX1, LX2>());
-  hipLaunchKernelGGL((k_fft4_x<T, LX1, LX2, NZ>), dim3(a.R * 4 * nkb), dim3(threads(a.B * a.nz, LX1, LX2)), lds, s, S, S,
-                     a.nx, Ly, a.nz, a.B, reinterpret_cast<const cplx<T>*>(a.tw_x),
-                     reinterpret_cast<const cplx<T>*>(a.gt));
+  hipLaunchKernelGGL((k_fft4_x<T, LX1, LX2, NZ>), dim3((nblocks + kXcds - 1) / kXcds * kXcds),
+                     dim3(threads(a.B * a.nz, LX1, LX2)), lds, s, S, S, a.nx, Ly, a.nz, a.B, nblocks,
+                     reinterpret_cast<const cplx<T>*>(a.tw_x), reinterpret_cast<const cplx<T>*>(a.gt));
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev) (void)hipEventRecord(ev[1], s);

@@ -38,6 +38,7 @@ struct ConvArgs {
 };
 
 constexpr int kNearGroupDev = 16;  // rows per matrix-core near-field group
+constexpr int kXcds = 8;           // accelerator complex dies; workgroups are dealt to them round-robin
 
 struct NearArgs {
   int R, ne, N, px, py;
