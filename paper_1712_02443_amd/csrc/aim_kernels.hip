@@ -483,7 +483,7 @@ __global__ void __launch_bounds__(256) k_near_mfma(const cplx<T>* __restrict__ u
   const int k0 = kh == 0 ? 0 : half, k1 = kh == 0 ? half : ncols;
   const cplx<T>* Ag = grp_A + int64_t(g0) * kNearGroupDev;
   typename M::acc_t accR = {}, accI = {};
-  constexpr int P = 4;  // K-steps per batch; the next batch is loaded ahead
+  constexpr int P = sizeof(T) == 4 ? 8 : 4;  // K-steps per batch; the next batch is loaded ahead
   auto fetch = [&](int k, cplx<T>& av, cplx<T>& bv) {
     if (k < k1) {
       const int col = cols_s[k + kq];
@@ -700,7 +700,8 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const cplx<float>* __restrict_
     av = (rowok && kk2 < ke) ? Mt[int64_t(kk2) * N + i0 + i] : cmk<float>(0, 0);
     bv = (colj >= 0 && kk2 < ke) ? xc[kk2] : cmk<float>(0, 0);
   };
-  f32x16 accR = {}, accI = {};
+  // three real products per complex step: re.re, im.im and (re + im).(re + im)
+  f32x16 accRR = {}, accII = {}, accSS = {};
   constexpr int P = 8;
   cplx<float> ca[P], cb[P];
 #pragma unroll
@@ -711,10 +712,9 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const cplx<float>* __restrict_
     for (int u = 0; u < P; ++u) fetch(k + 2 * P + 2 * u, na[u], nb[u]);
 #pragma unroll
     for (int u = 0; u < P; ++u) {
-      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[u].re, cb[u].re, accR, 0, 0, 0);
-      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(-ca[u].im, cb[u].im, accR, 0, 0, 0);
-      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[u].re, cb[u].im, accI, 0, 0, 0);
-      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[u].im, cb[u].re, accI, 0, 0, 0);
+      accRR = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[u].re, cb[u].re, accRR, 0, 0, 0);
+      accII = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[u].im, cb[u].im, accII, 0, 0, 0);
+      accSS = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[u].re + ca[u].im, cb[u].re + cb[u].im, accSS, 0, 0, 0);
     }
 #pragma unroll
     for (int u = 0; u < P; ++u) {
@@ -725,7 +725,8 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const cplx<float>* __restrict_
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int row = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);  // v_mfma_f32_32x32x2f32 output row
-    part[(w * kGemmRows + row) * (kGemmCols + 1) + (lane & 31)] = cmk<float>(accR[r], accI[r]);
+    part[(w * kGemmRows + row) * (kGemmCols + 1) + (lane & 31)] =
+        cmk<float>(accRR[r] - accII[r], accSS[r] - accRR[r] - accII[r]);
   }
   __syncthreads();
   gemm_reduce_store<float>(part, U, colbase, N, a.ne, i0);
