@@ -38,27 +38,19 @@ __device__ __forceinline__ void batched_copy(int n, Load f, Store g) {
 // Grid node g is written by exactly one element (its owner: the element whose
 // pitch-wide home cell contains g, the last row/column owning the tail).  The owner
 // gathers every basis of itself and of the neighbours whose stencil box covers g.
-// Lanes of a wave are 64 consecutive elements at the same element-local node, so
-// the gather table row is wave-uniform and u is read from its element-fastest copy.
+
+// Node (lx, ly, lz) of element (ix, iy), its owner: sum over the covering cells.
 template <typename T>
-__global__ void __launch_bounds__(256) k_project(const cplx<T>* __restrict__ uT, cplx<T>* __restrict__ Q,
-                                                 ProjArgs a, const T* __restrict__ Wp) {
-  const int ne64 = (a.ne + 63) & ~63;
-  const int nloc = a.ex * a.ey * a.ez;
-  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int m = int(gid % ne64);
-  const int64_t rest = gid / ne64;
-  const int L = __builtin_amdgcn_readfirstlane(int(rest % nloc));
-  const int r = __builtin_amdgcn_readfirstlane(int(rest / nloc));
-  if (r >= a.R || m >= a.ne) return;
-  const int lz = L % a.ez, ly = (L / a.ez) % a.ey, lx = L / (a.ez * a.ey);
-  const int ix = m % a.px, iy = m / a.px;
-  if (!((lx < a.pitch || ix == a.px - 1) && (ly < a.pitch || iy == a.py - 1))) return;
+__device__ __forceinline__ void project_node(const cplx<T>* __restrict__ ur, cplx<T>* __restrict__ Qr,
+                                             const ProjArgs& a, const T* __restrict__ Wp, int ix, int iy, int lx,
+                                             int ly, int lz) {
+  const int gx = ix * a.pitch + lx, gy = iy * a.pitch + ly;
+  if (gx >= a.nx || gy >= a.ny) return;  // home cell of the last column / row past the grid
+  const int m = iy * a.px + ix;
   const int64_t NQ = int64_t(a.N) * a.q3;
   cplx<T> acc[4];
 #pragma unroll
   for (int p = 0; p < 4; ++p) acc[p] = cmk<T>(0, 0);
-  const cplx<T>* ur = uT + int64_t(r) * a.N * a.ne;
   for (int dy = 0; ly + a.pitch * dy < a.ey; ++dy) {
     for (int dx = 0; lx + a.pitch * dx < a.ex; ++dx) {
       const int node = ((lx + a.pitch * dx) * a.ey + (ly + a.pitch * dy)) * a.ez + lz;
@@ -90,10 +82,89 @@ __global__ void __launch_bounds__(256) k_project(const cplx<T>* __restrict__ uT,
     }
   }
   const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
-  const int64_t g = (int64_t(ix * a.pitch + lx) * a.ny + (iy * a.pitch + ly)) * a.nz + lz;
-  cplx<T>* out = Q + int64_t(r) * 4 * nodes + g;
+  const int64_t g = (int64_t(gx) * a.ny + gy) * a.nz + lz;
 #pragma unroll
-  for (int p = 0; p < 4; ++p) out[p * nodes] = acc[p];
+  for (int p = 0; p < 4; ++p) Qr[p * nodes + g] = acc[p];
+}
+
+// Home cells (lx, ly < pitch): every element owns them.  Lanes of a wave are 64
+// consecutive elements at the same element-local node, so the gather table row is
+// wave-uniform and u is read from its element-fastest copy.
+template <typename T>
+__device__ __forceinline__ void project_tail(const cplx<T>* __restrict__ uT, cplx<T>* __restrict__ Q,
+                                             const ProjArgs& a, const T* __restrict__ Wp, int w, int lane);
+__device__ __forceinline__ int project_tail_waves(const ProjArgs& a);
+
+// One wave per workgroup: the tail waves (fewer, with longer gathers) come first.
+template <typename T>
+__global__ void __launch_bounds__(64) k_project(const cplx<T>* __restrict__ uT, cplx<T>* __restrict__ Q,
+                                                ProjArgs a, const T* __restrict__ Wp) {
+  const int ntail = project_tail_waves(a) * a.R;
+  if (int(blockIdx.x) < ntail) {
+    project_tail(uT, Q, a, Wp, blockIdx.x, threadIdx.x);
+    return;
+  }
+  const int ne64 = (a.ne + 63) & ~63;
+  const int nloc = a.pitch * a.pitch * a.ez;
+  const int64_t gid = int64_t(blockIdx.x - ntail) * 64 + threadIdx.x;
+  const int m = int(gid % ne64);
+  const int64_t rest = gid / ne64;
+  const int L = __builtin_amdgcn_readfirstlane(int(rest % nloc));
+  const int r = __builtin_amdgcn_readfirstlane(int(rest / nloc));
+  if (r >= a.R || m >= a.ne) return;
+  const int lz = L % a.ez, ly = (L / a.ez) % a.pitch, lx = L / (a.ez * a.pitch);
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  project_node(uT + int64_t(r) * a.N * a.ne, Q + int64_t(r) * 4 * nodes, a, Wp, m % a.px, m / a.px, lx, ly, lz);
+}
+
+// Nodes beyond the last home cells: the right strip (owned by the last column of
+// elements), the top strip (last row) and their corner (last element), wx = ex - pitch
+// and wy = ey - pitch nodes wide.  One wave per (strip, local node), lanes over the
+// strip's elements, so the gather table row stays wave-uniform.
+__device__ __forceinline__ int project_tail_waves(const ProjArgs& a) {
+  const int wx = max(a.ex - a.pitch, 0), wy = max(a.ey - a.pitch, 0);
+  return wx * a.pitch * a.ez * ((a.py + 63) / 64) + a.pitch * wy * a.ez * ((a.px + 63) / 64) + wx * wy * a.ez;
+}
+
+template <typename T>
+__device__ __forceinline__ void project_tail(const cplx<T>* __restrict__ uT, cplx<T>* __restrict__ Q,
+                                             const ProjArgs& a, const T* __restrict__ Wp, int w, int lane) {
+  const int wx = max(a.ex - a.pitch, 0), wy = max(a.ey - a.pitch, 0);
+  const int cy = (a.py + 63) / 64, cx = (a.px + 63) / 64;  // lane chunks per strip node
+  const int na = wx * a.pitch * a.ez * cy, nb = a.pitch * wy * a.ez * cx, nc = wx * wy * a.ez;
+  const int per_r = na + nb + nc;
+  const int r = w / per_r;
+  if (r >= a.R) return;
+  w -= r * per_r;
+  int ix, iy, lx, ly, lz;
+  if (w < na) {
+    const int L = w / cy;
+    iy = (w % cy) * 64 + lane;
+    ix = a.px - 1;
+    if (iy >= a.py) return;
+    lz = L % a.ez;
+    ly = (L / a.ez) % a.pitch;
+    lx = a.pitch + L / (a.pitch * a.ez);
+  } else if (w < na + nb) {
+    w -= na;
+    const int L = w / cx;
+    ix = (w % cx) * 64 + lane;
+    iy = a.py - 1;
+    if (ix >= a.px) return;
+    lz = L % a.ez;
+    ly = a.pitch + (L / a.ez) % wy;
+    lx = L / (wy * a.ez);
+  } else {
+    const int L = w - na - nb;
+    if (lane != 0) return;
+    ix = a.px - 1;
+    iy = a.py - 1;
+    lz = L % a.ez;
+    ly = a.pitch + (L / a.ez) % wy;
+    lx = a.pitch + L / (wy * a.ez);
+  }
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  project_node(uT + int64_t(r) * a.N * a.ne, Q + int64_t(r) * 4 * nodes, a, Wp, ix, iy, lx, ly, lz);
 }
 
 // [R][ne][N] -> [R][N][ne] (element-fastest copy of a vector); with the extents
@@ -869,8 +940,11 @@ static inline unsigned blocks_for(int64_t n, int bs) { return unsigned((n + bs -
 template <typename T>
 hipError_t launch_project(const cplx<T>* uT, cplx<T>* Q, const ProjArgs& a, const T* Wp, hipStream_t s) {
   const int64_t ne64 = (a.ne + 63) / 64 * 64;
-  const int64_t n = ne64 * a.ex * a.ey * a.ez * a.R;
-  hipLaunchKernelGGL(k_project<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, uT, Q, a, Wp);
+  const int64_t n = ne64 * a.pitch * a.pitch * a.ez * a.R;
+  const int wx = std::max(a.ex - a.pitch, 0), wy = std::max(a.ey - a.pitch, 0);
+  const int64_t tail_waves = int64_t(wx * a.pitch * a.ez * ((a.py + 63) / 64) + a.pitch * wy * a.ez * ((a.px + 63) / 64) +
+                                     wx * wy * a.ez) * a.R;
+  hipLaunchKernelGGL(k_project<T>, dim3(unsigned(tail_waves + blocks_for(n, 64))), dim3(64), 0, s, uT, Q, a, Wp);
   return hipGetLastError();
 }
 
