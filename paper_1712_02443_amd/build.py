@@ -16,7 +16,9 @@ SOURCES = ["setup.cpp", "aim_kernels.hip", "api.hip", "gmres.hip"]
 # Packed FP32 instructions are disabled for every device compile (hipcc's host pass
 # warns that it does not know the feature; that is harmless).
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
-             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             # lets the pruned FFT fold additions of known zeros (only the sign of zero results changes)
+             "-fno-signed-zeros"]
 
 
 def _hipcc() -> str:

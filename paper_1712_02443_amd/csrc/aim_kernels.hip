@@ -338,12 +338,14 @@ __global__ void __launch_bounds__(512) k_fft4_y_fwd(const cplx<T>* __restrict__ 
         const int y = e / nz, z = e - y * nz;
         buf[z * LD + f4_slot<L2>(y)] = v;
       });
-  for (int e = threadIdx.x; e < (L - ny_in) * nz; e += blockDim.x) {
-    const int z = e / (L - ny_in), y = ny_in + (e - z * (L - ny_in));
+  // zero padding, up to the last row the pruned first pass reads
+  constexpr int kRead = (L1 / 2 + 1) * L2;
+  for (int e = threadIdx.x; e < (kRead - ny_in) * nz; e += blockDim.x) {
+    const int y = ny_in + e / nz, z = e - (y - ny_in) * nz;
     buf[z * LD + f4_slot<L2>(y)] = cmk<T>(0, 0);
   }
   __syncthreads();
-  fft4_lines<T, L1, L2, true>(buf, nz, tw);
+  fft4_lines<T, L1, L2, true, true, false>(buf, nz, tw);
   cplx<T>* dst = out + plane * int64_t(L) * nz;
   for (int e = threadIdx.x; e < L * nz; e += blockDim.x) {
     const int y = e / nz, z = e - y * nz;
@@ -375,22 +377,29 @@ __global__ void __launch_bounds__(512) k_fft4_x(const cplx<T>* in, cplx<T>* out,
   const cplx<T>* src = in + plane * int64_t(nx_in) * row + int64_t(kb) * lines;
   cplx<T>* dst = out + plane * int64_t(nx_in) * row + int64_t(kb) * lines;
   for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = twg[i];
-  batched_copy<8, T>(
-      nx_in * lines,
-      [&](int e) {
-        const int x = e / lines, l = e - x * lines;
-        return src[int64_t(x) * row + l];
-      },
-      [&](int e, cplx<T> v) {
-        const int x = e / lines, l = e - x * lines;
-        buf[l * LD + f4_slot<L2>(x)] = v;
-      });
-  for (int e = threadIdx.x; e < (L - nx_in) * lines; e += blockDim.x) {
-    const int l = e / (L - nx_in), x = nx_in + (e - l * (L - nx_in));
-    buf[l * LD + f4_slot<L2>(x)] = cmk<T>(0, 0);
+  // thread -> (row phase x0, line l); rows x0, x0 + rpp, ... up to the last row the
+  // pruned first pass reads (zero beyond nx_in)
+  constexpr int kRead = (L1 / 2 + 1) * L2;
+  const int rpp = int(blockDim.x) / lines;
+  const int l = int(threadIdx.x) % lines, x0 = int(threadIdx.x) / lines;
+  if (x0 < rpp) {
+    constexpr int U = 8;
+    for (int xb = x0; xb < kRead; xb += U * rpp) {
+      cplx<T> v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int x = xb + u * rpp;
+        v[u] = x < nx_in ? src[int64_t(x) * row + l] : cmk<T>(0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int x = xb + u * rpp;
+        if (x < kRead) buf[l * LD + f4_slot<L2>(x)] = v[u];
+      }
+    }
   }
   __syncthreads();
-  fft4_lines<T, L1, L2, true>(buf, lines, tw);
+  fft4_lines<T, L1, L2, true, true, false>(buf, lines, tw);
   const int half_y = Ly / 2 + 1;
   for (int it = threadIdx.x; it < L * B; it += blockDim.x) {
     const int b = it / L, k = it - b * L;
@@ -416,11 +425,9 @@ __global__ void __launch_bounds__(512) k_fft4_x(const cplx<T>* in, cplx<T>* out,
     }
   }
   __syncthreads();
-  fft4_lines<T, L1, L2, false>(buf, lines, tw);
-  for (int e = threadIdx.x; e < nx_in * lines; e += blockDim.x) {
-    const int x = e / lines, l = e - x * lines;
-    dst[int64_t(x) * row + l] = buf[l * LD + f4_slot<L2>(x)];
-  }
+  fft4_lines<T, L1, L2, false, false, true>(buf, lines, tw);
+  if (x0 < rpp)
+    for (int x = x0; x < nx_in; x += rpp) dst[int64_t(x) * row + l] = buf[l * LD + f4_slot<L2>(x)];
 }
 
 template <typename T, int L1, int L2, int NZ>
@@ -441,7 +448,7 @@ __global__ void __launch_bounds__(512) k_fft4_y_inv(const cplx<T>* __restrict__ 
         buf[z * LD + f4_slot<L2>(y)] = v;
       });
   __syncthreads();
-  fft4_lines<T, L1, L2, false>(buf, nz, tw);
+  fft4_lines<T, L1, L2, false, false, true>(buf, nz, tw);
   cplx<T>* dst = out + plane * int64_t(ny) * nz;
   for (int e = threadIdx.x; e < ny * nz; e += blockDim.x) {
     const int y = e / nz, z = e - y * nz;

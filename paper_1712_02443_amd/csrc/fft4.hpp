@@ -145,16 +145,21 @@ constexpr int f4_ld() {
 
 // Transform nlines lines at buf + line * f4_ld in place.  tw[t] = exp(-2 pi i t / L)
 // for t < L (LDS).  Needs blockDim.x >= nlines * max(L1, L2); ends with a barrier.
-template <typename T, int L1, int L2, bool FWD>
+// Pruning: ZERO_TAIL declares the input zero beyond index L / 2 (a line zero-padded
+// from at most L / 2 + 1 values), so pass A keeps only rows x1 <= L1 / 2 and the DFTs
+// fold the zeros away; HALF_OUT keeps only outputs up to index L / 2 (the unpadded
+// part), so pass B stores, and computes, outputs k2 <= L2 / 2 only.
+template <typename T, int L1, int L2, bool FWD, bool ZERO_TAIL = false, bool HALF_OUT = false>
 __device__ __forceinline__ void fft4_lines(cplx<T>* buf, int nlines, const cplx<T>* tw) {
   constexpr int P = L2 + 1, LD = f4_ld<L1, L2>();
+  constexpr int NA = ZERO_TAIL ? L1 / 2 + 1 : L1, NB = HALF_OUT ? L2 / 2 + 1 : L2;
   // pass A: one length-L1 DFT per (line, x2), then the twiddles W_L^{x2 k1}
   if (int(threadIdx.x) < nlines * L2) {
     const int line = threadIdx.x / L2, x2 = threadIdx.x - line * L2;
     cplx<T>* b = buf + line * LD;
     cplx<T> v[L1];
 #pragma unroll
-    for (int x1 = 0; x1 < L1; ++x1) v[x1] = b[x1 * P + x2];
+    for (int x1 = 0; x1 < L1; ++x1) v[x1] = x1 < NA ? b[x1 * P + x2] : cmk<T>(0, 0);
     fft4::RegDft<T, L1, FWD>::run(v);
 #pragma unroll
     for (int k1 = 1; k1 < L1; ++k1) v[k1] = FWD ? cmul(v[k1], tw[x2 * k1]) : cmulc(v[k1], tw[x2 * k1]);
@@ -176,7 +181,7 @@ __device__ __forceinline__ void fft4_lines(cplx<T>* buf, int nlines, const cplx<
     fft4::RegDft<T, L2, FWD>::run(u);
     cplx<T>* o = buf + line * LD;
 #pragma unroll
-    for (int k2 = 0; k2 < L2; ++k2) o[f4_slot<L2>(k1 + L1 * k2)] = u[k2];
+    for (int k2 = 0; k2 < NB; ++k2) o[f4_slot<L2>(k1 + L1 * k2)] = u[k2];
   }
   __syncthreads();
 }
