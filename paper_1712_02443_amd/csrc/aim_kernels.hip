@@ -551,24 +551,28 @@ __global__ void __launch_bounds__(256) k_near_mfma(const cplx<T>* __restrict__ u
   const int mblk = blockIdx.x * 32, g = blockIdx.y, r = blockIdx.z;
   const int jcol = lane & 15, kq = lane >> 4;
   const int mb = mblk + eh * 16 + jcol;
-  const bool validb = mb < a.ne;
   const int ix = mb % a.px, iy = mb / a.px;
-  const cplx<T>* ur = uT + int64_t(r) * a.N * a.ne;
+  // bit (dy + 2) 5 + (dx + 2): the neighbour at lattice offset (dx, dy) exists
+  unsigned vmask = 0;
+  if (mb < a.ne)
+    for (int dy = -2; dy <= 2; ++dy)
+      for (int dx = -2; dx <= 2; ++dx)
+        if (ix + dx >= 0 && ix + dx < a.px && iy + dy >= 0 && iy + dy < a.py) vmask |= 1u << ((dy + 2) * 5 + dx + 2);
+  const cplx<T>* ur = uT + int64_t(r) * a.N * a.ne + mb;
   const int g0 = a.grp_ptr[g], ncols = a.grp_ptr[g + 1] - g0;
   for (int t = threadIdx.x; t < ncols; t += blockDim.x) cols_s[t] = a.grp_col[g0 + t];
   __syncthreads();
   const int half = (ncols / 8) * 4;  // first half, a multiple of the K step (4)
   const int k0 = kh == 0 ? 0 : half, k1 = kh == 0 ? half : ncols;
   const cplx<T>* Ag = grp_A + int64_t(g0) * kNearGroupDev;
-  typename M::acc_t accR = {}, accI = {};
+  // three real products per complex step: re.re, im.im and (re + im).(re + im)
+  typename M::acc_t accRR = {}, accII = {}, accSS = {};
   constexpr int P = sizeof(T) == 4 ? 8 : 4;  // K-steps per batch; the next batch is loaded ahead
   auto fetch = [&](int k, cplx<T>& av, cplx<T>& bv) {
     if (k < k1) {
       const int col = cols_s[k + kq];
-      const int np_ = col & 0xFFFF;
-      const int jx = ix + ((col >> 16) & 0xFF) - 8, jy = iy + ((col >> 24) & 0xFF) - 8;
-      const bool ok = validb && jx >= 0 && jx < a.px && jy >= 0 && jy < a.py;
-      bv = ok ? ur[int64_t(np_) * a.ne + jy * a.px + jx] : cmk<T>(0, 0);
+      const bool ok = (vmask >> (col & 31)) & 1u;
+      bv = ok ? ur[col >> 5] : cmk<T>(0, 0);
       av = Ag[int64_t(k + kq) * kNearGroupDev + jcol];
     } else {
       av = cmk<T>(0, 0);
@@ -584,10 +588,9 @@ __global__ void __launch_bounds__(256) k_near_mfma(const cplx<T>* __restrict__ u
     for (int u = 0; u < P; ++u) fetch(k + 4 * P + 4 * u, na[u], nb[u]);
 #pragma unroll
     for (int u = 0; u < P; ++u) {
-      accR = M::mma(ca[u].re, cb[u].re, accR);
-      accR = M::mma(-ca[u].im, cb[u].im, accR);
-      accI = M::mma(ca[u].re, cb[u].im, accI);
-      accI = M::mma(ca[u].im, cb[u].re, accI);
+      accRR = M::mma(ca[u].re, cb[u].re, accRR);
+      accII = M::mma(ca[u].im, cb[u].im, accII);
+      accSS = M::mma(ca[u].re + ca[u].im, cb[u].re + cb[u].im, accSS);
     }
 #pragma unroll
     for (int u = 0; u < P; ++u) {
@@ -597,7 +600,8 @@ __global__ void __launch_bounds__(256) k_near_mfma(const cplx<T>* __restrict__ u
   }
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr)
-    tile[kh][mfma16_row<T>(lane, rr)][eh * 16 + jcol] = cmk<T>(accR[rr], accI[rr]);
+    tile[kh][mfma16_row<T>(lane, rr)][eh * 16 + jcol] =
+        cmk<T>(accRR[rr] - accII[rr], accSS[rr] - accRR[rr] - accII[rr]);
   __syncthreads();
   // output in group-slot order: 16 consecutive slots per element
   const int s0 = g * kNearGroupDev;

@@ -426,10 +426,23 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
     op->nbr = upload(op, nbr.data(), nbr.size());
     op->offsets_d = upload(op, st.offsets.data(), st.offsets.size());
     op->grp_ptr = upload(op, st.grp_ptr.data(), st.grp_ptr.size());
-    op->grp_col = upload(op, st.grp_col.data(), st.grp_col.size());
+    {
+      // matrix-core near-field columns as (n' ne + dx + dy px) << 5 | (dy + 2) 5 + (dx + 2):
+      // the offset of the neighbour's u from the element's own and a 5 x 5 validity slot
+      std::vector<int32_t> gc(st.grp_col.size());
+      const int64_t lim = int64_t(1) << 25;
+      for (size_t i = 0; i < gc.size(); ++i) {
+        const int c = st.grp_col[i];
+        const int np_ = c & 0xFFFF, dx = ((c >> 16) & 0xFF) - 8, dy = ((c >> 24) & 0xFF) - 8;
+        const int64_t off = int64_t(np_) * op->ne + dx + int64_t(dy) * a.px;
+        if (std::abs(dx) > 2 || std::abs(dy) > 2 || off >= lim || off <= -lim) op->near_mfma = false;
+        gc[i] = int32_t(off * 32 + (dy + 2) * 5 + (dx + 2));
+      }
+      op->grp_col = upload(op, gc.data(), gc.size());
+    }
     op->grp_row = upload(op, st.grp_row.data(), st.grp_row.size());
     op->slot_of = upload(op, st.slot_of.data(), st.slot_of.size());
-    if (const char* env = std::getenv("AIMM_NEAR_CSR")) op->near_mfma = std::atoi(env) == 0;
+    if (const char* env = std::getenv("AIMM_NEAR_CSR")) op->near_mfma = op->near_mfma && std::atoi(env) == 0;
     // register-DFT FFT passes where both padded lengths have a compiled factorisation
     op->fft4 = fft4_supported(op->Lx) && fft4_supported(op->Ly);
     if (const char* env = std::getenv("AIMM_FFT4")) op->fft4 = op->fft4 && std::atoi(env) != 0;
