@@ -26,6 +26,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 536870912  # the plain device copy that calibrates the byte counters
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_jc32x32_fp32_product.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1712_02443_amd", "csrc", "aim_kernels.hip")
+# device kernel name prefixes (FP32 product) -> per-kernel keys of this benchmark
+KERNEL_KEYS = [("k_gemm_f32", "macro_gemm"), ("k_project<float>", "project"), ("k_fft4_y_fwd<float", "fft_y_fwd"),
+               ("k_fft_y_fwd<float>", "fft_y_fwd"), ("k_fft4_x<float", "fft_x_conv"), ("k_fft_x<float, 0>", "fft_x_conv"),
+               ("k_fft4_y_inv<float", "fft_y_inv"), ("k_fft_y_inv<float>", "fft_y_inv"),
+               ("k_near_mfma<float>", "near_field"), ("k_near<float>", "near_field"), ("k_interp<float, 0", "interp_d")]
 FP32_MFMA_PEAK_TFLOPS = 157.3
 # FP32 vector FMA without packed (two-wide) instructions, which this build disables:
 # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
@@ -51,6 +59,67 @@ def kernel_model(info: dict, R: int, bytes_per: int) -> dict:
         "near_field": {"flops": 8.0 * info["near_nnz"] * info["n_elem"] * R, "bytes": 2 * vec},
         "interp_d": {"bytes": grid + 3 * vec},
     }
+
+
+def source_sha256() -> str:
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def summarize_counters(fetch_csv: str, write_csv: str, out_md: str, command: str) -> None:
+    """Per-launch HBM bytes of the FP32 product kernels from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), scaled by what the same counters read
+    for the plain 536,870,912-byte device copy of --profile-products."""
+    import csv
+
+    def load(path, counter):
+        per, copy = {}, []
+        for row in csv.DictReader(open(path)):
+            if row["Counter_Name"] != counter:
+                continue
+            name = row["Kernel_Name"].replace("void ", "").replace("aimm::", "")
+            val = float(row["Counter_Value"]) * 1024.0
+            if "copyBuffer" in name:
+                copy.append(val)
+                continue
+            for prefix, key in KERNEL_KEYS:
+                if name.startswith(prefix):
+                    per.setdefault(key, []).append(val)
+        return per, max(copy)
+
+    fetch, copy_f = load(fetch_csv, "FETCH_SIZE")
+    write, copy_w = load(write_csv, "WRITE_SIZE")
+    kf, kw = COPY_BYTES / copy_f, COPY_BYTES / copy_w
+    lines = ["# HBM traffic per launch, FP32 product kernels, 32x32 Jerusalem-cross array", "",
+             "Commands (from the repository root, libaimm.so built):", "", "```", command, "```", "",
+             f"Calibration: the {COPY_BYTES}-byte device copy read FETCH_SIZE {copy_f:.0f} B and WRITE_SIZE "
+             f"{copy_w:.0f} B, so fetch counts are scaled by {kf:.4f} and write counts by {kw:.4f}.", "",
+             "| kernel | launches | fetch bytes | write bytes | total bytes |", "|---|---|---|---|---|"]
+    for _, key in KERNEL_KEYS:
+        if key in fetch and key in write and f"| {key} |" not in "\n".join(lines):
+            f = sum(fetch[key]) / len(fetch[key]) * kf
+            w = sum(write[key]) / len(write[key]) * kw
+            lines.append(f"| {key} | {len(fetch[key])} | {f:.0f} | {w:.0f} | {f + w:.0f} |")
+    lines += ["", f"source-sha256 aim_kernels.hip: {source_sha256()}", ""]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines))
+
+
+def measured_traffic(kernel: str):
+    """Bytes per launch of `kernel` from the committed counter summary, or None when
+    the summary is missing or was taken from another version of the kernel source."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    if f"source-sha256 aim_kernels.hip: {source_sha256()}" not in text:
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 5 and cells[0] == kernel:
+            return float(cells[4])
+    return None
 
 
 def cpu_baseline(wl, budget_s: float = 20.0) -> dict:
@@ -91,7 +160,13 @@ def main() -> int:
     ap.add_argument("--profile-products", type=int, default=0,
                     help="only run this many FP32 and FP64 products and a 512 MiB device copy "
                          "(the copy calibrates hardware byte counters), then exit")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD"),
+                    help="write the per-launch HBM traffic summary from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--counter-command", default="", help="command line recorded in the summary")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, command=args.counter_command)
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the path shards over right-hand sides or x-slabs, see DESIGN.md)", file=sys.stderr)
@@ -199,15 +274,17 @@ def main() -> int:
     kt64 = op.time_kernels(x64, precision=AIM_FP64, reps=args.kernel_reps)
     model = kernel_model(info, 1, 8)
     dom = max(kt, key=kt.get)
+    traffic = measured_traffic(dom)
     if "flops" in model[dom]:
+        # the macromodel GEMM and the near field run on the FP32 matrix cores
         ach = model[dom]["flops"] / (kt[dom] * 1e-3) / 1e12
-        peak = FP32_MFMA_PEAK_TFLOPS if dom == "macro_gemm" else FP32_VALU_PEAK_TFLOPS
-        roof = {"kernel": dom, "bound": "mfma" if dom == "macro_gemm" else "alu", "achieved": ach, "peak": peak,
-                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None}
+        roof = {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": FP32_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / FP32_MFMA_PEAK_TFLOPS, "traffic": traffic,
+                "algorithmic_bytes": model[dom]["bytes"]}
     else:
         ach = model[dom]["bytes"] / (kt[dom] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None}
+                "frac": ach / HBM_PEAK_GBS, "traffic": traffic}
     per_kernel = {}
     for k, ms in kt.items():
         m = model[k]
