@@ -559,25 +559,23 @@ __global__ void __launch_bounds__(256) k_near_mfma(const cplx<T>* __restrict__ u
       for (int dx = -2; dx <= 2; ++dx)
         if (ix + dx >= 0 && ix + dx < a.px && iy + dy >= 0 && iy + dy < a.py) vmask |= 1u << ((dy + 2) * 5 + dx + 2);
   const cplx<T>* ur = uT + int64_t(r) * a.N * a.ne + mb;
+  const cplx<T>* zero = static_cast<const cplx<T>*>(a.zero);
+  // the group's columns plus one prefetch batch past them (the next group's or the
+  // zero tail): every load below is unconditional, so the prefetch stays in flight
   const int g0 = a.grp_ptr[g], ncols = a.grp_ptr[g + 1] - g0;
-  for (int t = threadIdx.x; t < ncols; t += blockDim.x) cols_s[t] = a.grp_col[g0 + t];
+  for (int t = threadIdx.x; t < ncols + kNearColTailDev; t += blockDim.x) cols_s[t] = a.grp_col[g0 + t];
   __syncthreads();
-  const int half = (ncols / 8) * 4;  // first half, a multiple of the K step (4)
-  const int k0 = kh == 0 ? 0 : half, k1 = kh == 0 ? half : ncols;
+  const int half = ncols / 2;  // column counts are multiples of two K halves of whole batches
+  const int k0 = kh == 0 ? 0 : half, k1 = k0 + half;
   const cplx<T>* Ag = grp_A + int64_t(g0) * kNearGroupDev;
   // three real products per complex step: re.re, im.im and (re + im).(re + im)
   typename M::acc_t accRR = {}, accII = {}, accSS = {};
   constexpr int P = sizeof(T) == 4 ? 8 : 4;  // K-steps per batch; the next batch is loaded ahead
   auto fetch = [&](int k, cplx<T>& av, cplx<T>& bv) {
-    if (k < k1) {
-      const int col = cols_s[k + kq];
-      const bool ok = (vmask >> (col & 31)) & 1u;
-      bv = ok ? ur[col >> 5] : cmk<T>(0, 0);
-      av = Ag[int64_t(k + kq) * kNearGroupDev + jcol];
-    } else {
-      av = cmk<T>(0, 0);
-      bv = cmk<T>(0, 0);
-    }
+    const int col = cols_s[k + kq];
+    const bool ok = (vmask >> (col & 31)) & 1u;
+    bv = *(ok ? ur + (col >> 5) : zero);  // absent neighbours read a zero
+    av = Ag[int64_t(k + kq) * kNearGroupDev + jcol];
   };
   cplx<T> ca[P], cb[P];
 #pragma unroll
@@ -769,18 +767,20 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const cplx<float>* __restrict_
   gemm_tile_setup(a, t, cols, colbase);
   __syncthreads();
   const int N = a.N, i0 = blockIdx.y * kGemmRows;
-  const cplx<float>* Mt = M + int64_t(t) * N * N;
+  const cplx<float>* Mt = M + int64_t(t) * a.Krows * N;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = lane & 31, kk = lane >> 5;
   const int colj = cols[lane & 31];
-  const bool rowok = i0 + i < N;
-  const int kq = ((N + 7) / 8) * 2;  // per-wave range, a multiple of the K step (2)
-  const int kb = w * kq, ke = min(N, kb + kq);
-  const cplx<float>* xc = X + (colj >= 0 ? int64_t(colj) * N : 0);
+  // Every operand load is unconditional, so the prefetched batch stays in flight:
+  // rows past N and padding columns read valid data whose outputs are discarded, and
+  // the K range of each wave runs over M's zero rows past N (X is clamped there).
+  const int ir = min(i0 + i, N - 1);
+  const int kq = a.Kq, kb = w * kq, ke = kb + kq;
+  const cplx<float>* xc = X + int64_t(max(colj, 0)) * N;
   auto fetch = [&](int k, cplx<float>& av, cplx<float>& bv) {
     const int kk2 = k + kk;
-    av = (rowok && kk2 < ke) ? Mt[int64_t(kk2) * N + i0 + i] : cmk<float>(0, 0);
-    bv = (colj >= 0 && kk2 < ke) ? xc[kk2] : cmk<float>(0, 0);
+    av = Mt[int64_t(kk2) * N + ir];
+    bv = xc[min(kk2, N - 1)];
   };
   // three real products per complex step: re.re, im.im and (re + im).(re + im)
   f32x16 accRR = {}, accII = {}, accSS = {};
@@ -824,24 +824,23 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const cplx<double>* __restrict
   gemm_tile_setup(a, t, cols, colbase);
   __syncthreads();
   const int N = a.N, i0 = blockIdx.y * kGemmRows;
-  const cplx<double>* Mt = M + int64_t(t) * N * N;
+  const cplx<double>* Mt = M + int64_t(t) * a.Krows * N;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, kk = lane >> 4;
-  int colq[2];
-  bool rowok[2];
+  int colq[2], rowq[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    colq[q] = cols[q * 16 + l16];
-    rowok[q] = i0 + q * 16 + l16 < N;
+    colq[q] = max(cols[q * 16 + l16], 0);  // padding columns: any valid column, outputs discarded
+    rowq[q] = min(i0 + q * 16 + l16, N - 1);
   }
-  const int kq = ((N + 15) / 16) * 4;  // per-wave range, a multiple of the K step (4)
-  const int kb = w * kq, ke = min(N, kb + kq);
+  // unconditional loads over M's zero rows past N, as in the FP32 kernel
+  const int kq = a.Kq, kb = w * kq, ke = kb + kq;
   auto fetch = [&](int k, cplx<double>* av, cplx<double>* bv) {
     const int kk2 = k + kk;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      av[q] = (rowok[q] && kk2 < ke) ? Mt[int64_t(kk2) * N + i0 + q * 16 + l16] : cmk<double>(0, 0);
-      bv[q] = (colq[q] >= 0 && kk2 < ke) ? X[int64_t(colq[q]) * N + kk2] : cmk<double>(0, 0);
+      av[q] = Mt[int64_t(kk2) * N + rowq[q]];
+      bv[q] = X[int64_t(colq[q]) * N + min(kk2, N - 1)];
     }
   };
   f64x4 accR[2][2] = {}, accI[2][2] = {};
@@ -1049,8 +1048,8 @@ hipError_t launch_near(const cplx<T>* uT, cplx<T>* nf, const NearArgs& a, const 
     // element blocks fastest, so consecutive workgroups (spread over the XCDs) share
     // the rows of u they read
     const dim3 g((a.ne + 31) / 32, (a.N + kNearGroupDev - 1) / kNearGroupDev, a.R);
-    hipLaunchKernelGGL(k_near_mfma<T>, g, dim3(256), sizeof(int) * size_t(a.grp_max_cols), s, uT, nf, a,
-                       reinterpret_cast<const cplx<T>*>(a.grp_A));
+    hipLaunchKernelGGL(k_near_mfma<T>, g, dim3(256), sizeof(int) * size_t(a.grp_max_cols + kNearColTailDev), s, uT,
+                       nf, a, reinterpret_cast<const cplx<T>*>(a.grp_A));
   } else {
     const dim3 g((a.N + kNearRows - 1) / kNearRows, (a.ne + 63) / 64, a.R);
     hipLaunchKernelGGL(k_near<T>, g, dim3(256), 0, s, uT, nf, a, near_val);

@@ -38,6 +38,7 @@ struct ConvArgs {
 };
 
 constexpr int kNearGroupDev = 16;  // rows per matrix-core near-field group
+constexpr int kNearColTailDev = 32;  // zero columns after the last group
 constexpr int kXcds = 8;           // accelerator complex dies; workgroups are dealt to them round-robin
 
 struct NearArgs {
@@ -50,6 +51,7 @@ struct NearArgs {
   const int* grp_row;  // [groups][kNearGroupDev] row of each group slot, -1 for none
   const int* slot_of;  // [N] group slot of each row
   const void* grp_A;
+  const void* zero;    // one zero complex value (read for absent neighbours)
   int grp_max_cols;    // largest column count of a group (LDS staging of its columns)
   int ld_nf;           // slots per element of the output (groups x kNearGroupDev)
 };
@@ -77,8 +79,15 @@ inline size_t interp_lds_bytes(const InterpArgs& a, size_t elem) {
 
 constexpr int kGemmColsHost = 32;  // output columns per macromodel GEMM workgroup
 
+// Macromodel rows on the device: per kind, Krows = 4 Kq + kGemmKTail columns of M
+// (column-major), zero past N; Kq is the per-wave K range, a multiple of 16.
+constexpr int kGemmKTail = 16;  // one prefetch batch past the last wave's range
+inline int gemm_kq(int N) { return (N + 63) / 64 * 16; }
+inline int gemm_krows(int N) { return 4 * gemm_kq(N) + kGemmKTail; }
+
 struct GemmArgs {
   int N, R, n_types, ne;
+  int Kq, Krows;
   int tile_start[kMaxTypes + 1];
   int type_count[kMaxTypes];
   int col_start[kMaxTypes];

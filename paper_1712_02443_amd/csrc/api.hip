@@ -179,6 +179,7 @@ static NearArgs near_args(aim_op* op, int R) {
   a.grp_row = op->grp_row;
   a.slot_of = op->slot_of;
   a.grp_A = nullptr;
+  a.zero = op->zero;
   a.grp_max_cols = op->st.grp_max_cols;
   a.ld_nf = int(op->st.grp_row.size());
   a.near_ptr = op->near_ptr;
@@ -232,6 +233,8 @@ static GemmArgs gemm_args(aim_op* op, int R) {
   a.ne = op->ne;
   a.R = R;
   a.n_types = op->n_types;
+  a.Kq = gemm_kq(op->N);
+  a.Krows = gemm_krows(op->N);
   a.col_list = op->col_list;
   a.tile_start[0] = 0;
   for (int t = 0; t < op->n_types; ++t) {
@@ -442,6 +445,10 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
     }
     op->grp_row = upload(op, st.grp_row.data(), st.grp_row.size());
     op->slot_of = upload(op, st.slot_of.data(), st.slot_of.size());
+    {
+      const cplx<double> z{0.0, 0.0};
+      op->zero = upload(op, &z, 1);
+    }
     if (const char* env = std::getenv("AIMM_NEAR_CSR")) op->near_mfma = op->near_mfma && std::atoi(env) == 0;
     // register-DFT FFT passes where both padded lengths have a compiled factorisation
     op->fft4 = fft4_supported(op->Lx) && fft4_supported(op->Ly);
@@ -527,18 +534,25 @@ int aim_set_macromodels(aim_op* op, const double* M) {
     set_error("op was built without device data (aim_build_host)");
     return AIM_ESTATE;
   }
-  const size_t n = size_t(op->n_types) * op->N * op->N;
+  // device copy: per kind, gemm_krows(N) columns (column-major), zero past N
+  const size_t N = size_t(op->N), kr = size_t(gemm_krows(op->N));
+  const size_t n = size_t(op->n_types) * kr * N;
   try {
     if (!op->p64.M) {
       op->p64.M = op->mem.alloc<cplx<double>>(n);
       op->p32.M = op->mem.alloc<cplx<float>>(n);
     }
-    std::vector<cplx<float>> m32(n);
-    for (size_t i = 0; i < n; ++i) {
-      m32[i].re = float(M[2 * i]);
-      m32[i].im = float(M[2 * i + 1]);
-    }
-    AIM_HIP(hipMemcpy(op->p64.M, M, n * sizeof(cplx<double>), hipMemcpyHostToDevice));
+    std::vector<cplx<double>> m64(n, cplx<double>{0.0, 0.0});
+    std::vector<cplx<float>> m32(n, cplx<float>{0.0f, 0.0f});
+    for (size_t t = 0; t < size_t(op->n_types); ++t)
+      for (size_t e = 0; e < N * N; ++e) {
+        const size_t src = t * N * N + e, dst = t * kr * N + e;
+        m64[dst].re = M[2 * src];
+        m64[dst].im = M[2 * src + 1];
+        m32[dst].re = float(M[2 * src]);
+        m32[dst].im = float(M[2 * src + 1]);
+      }
+    AIM_HIP(hipMemcpy(op->p64.M, m64.data(), n * sizeof(cplx<double>), hipMemcpyHostToDevice));
     AIM_HIP(hipMemcpy(op->p32.M, m32.data(), n * sizeof(cplx<float>), hipMemcpyHostToDevice));
   } catch (const std::bad_alloc&) {
     set_error("device allocation failed");

@@ -106,6 +106,7 @@ struct aim_op {
       *near_col = nullptr;
   int* offsets_d = nullptr;
   int *grp_ptr = nullptr, *grp_col = nullptr, *grp_row = nullptr, *slot_of = nullptr;
+  aimm::cplx<double>* zero = nullptr;  // one zero value (16 bytes; also read as complex64)
   bool near_mfma = true;
   bool fft4 = false;  // register-DFT FFT passes
   int interp_tx = 0, interp_ty = 0;  // 0 = automatic  // [n_off][2] lattice offsets of the near-field blocks

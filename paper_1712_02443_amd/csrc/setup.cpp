@@ -568,7 +568,8 @@ void build_setup(const SurfaceIn& s, const ArrayIn& a, Setup& out) {
     }
     int k = 0;
     for (auto& kv : col_index) kv.second = k++;
-    const int kpad = (k + 3) / 4 * 4;
+    // a multiple of two K halves of whole prefetch batches, so the kernel needs no bounds tests
+    const int kpad = (k + kNearColAlign - 1) / kNearColAlign * kNearColAlign;
     const size_t base = out.grp_col.size();
     // device form of a column: n' | (dx + 8) << 16 | (dy + 8) << 24 (lattice offset inline)
     auto dev_col = [&](int32_t c) {
@@ -589,6 +590,10 @@ void build_setup(const SurfaceIn& s, const ArrayIn& a, Setup& out) {
     out.grp_ptr[g + 1] = int32_t(out.grp_col.size());
     out.grp_max_cols = std::max(out.grp_max_cols, kpad);
   }
+  // one more batch of zero columns after the last group: the final prefetch reads it
+  const int32_t self_col = int32_t((8 << 16) | (8 << 24));
+  for (int p = 0; p < kNearColTail; ++p) out.grp_col.push_back(self_col);
+  out.grp_A.resize(out.grp_col.size() * kNearGroup, cd(0.0));
 }
 
 void plane_wave_local(const SurfaceIn& s, double k, double theta, double phi, int pol,
