@@ -318,6 +318,25 @@ __global__ void __launch_bounds__(256) k_fft_y_inv(const cplx<T>* in, cplx<T>* o
   }
 }
 
+// tw[0, L) <- twg, every load issued before the first LDS store
+template <typename T, int L>
+__device__ __forceinline__ void load_twiddles(cplx<T>* tw, const cplx<T>* __restrict__ twg) {
+  constexpr int kMaxPer = 8;
+  const int per = (L + int(blockDim.x) - 1) / int(blockDim.x);
+  cplx<T> v[kMaxPer];
+#pragma unroll
+  for (int u = 0; u < kMaxPer; ++u) {
+    const int i = min(int(threadIdx.x) + u * int(blockDim.x), L - 1);
+    v[u] = twg[i];
+  }
+#pragma unroll
+  for (int u = 0; u < kMaxPer; ++u) {
+    const int i = int(threadIdx.x) + u * int(blockDim.x);
+    if (u < per && i < L) tw[i] = v[u];
+  }
+  for (int i = int(threadIdx.x) + kMaxPer * int(blockDim.x); i < L; i += blockDim.x) tw[i] = twg[i];
+}
+
 // ---- step (ii) with register DFTs (four-step, natural order) for L = L1 L2 --------
 // Same three passes as above; lines are held at the padded slots of fft4_lines, and
 // spectra are in natural order, so no digit-reversal tables are involved.
@@ -331,7 +350,7 @@ __global__ void __launch_bounds__(512) k_fft4_y_fwd(const cplx<T>* __restrict__ 
   cplx<T>* buf = tw + L;
   const int64_t plane = blockIdx.x;
   const cplx<T>* src = in + plane * int64_t(ny_in) * nz;
-  for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = twg[i];
+  load_twiddles<T, L>(tw, twg);
   batched_copy<8, T>(
       ny_in * nz, [&](int e) { return src[e]; },
       [&](int e, cplx<T> v) {
@@ -376,7 +395,7 @@ __global__ void __launch_bounds__(512) k_fft4_x(const cplx<T>* in, cplx<T>* out,
   const int64_t row = int64_t(Ly) * nz;  // stride between x rows
   const cplx<T>* src = in + plane * int64_t(nx_in) * row + int64_t(kb) * lines;
   cplx<T>* dst = out + plane * int64_t(nx_in) * row + int64_t(kb) * lines;
-  for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = twg[i];
+  load_twiddles<T, L>(tw, twg);
   // thread -> (row phase x0, line l); rows x0, x0 + rpp, ... up to the last row the
   // pruned first pass reads (zero beyond nx_in)
   constexpr int kRead = (L1 / 2 + 1) * L2;
@@ -440,7 +459,7 @@ __global__ void __launch_bounds__(512) k_fft4_y_inv(const cplx<T>* __restrict__ 
   cplx<T>* buf = tw + L;
   const int64_t plane = blockIdx.x;
   const cplx<T>* src = in + plane * int64_t(L) * nz;
-  for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = twg[i];
+  load_twiddles<T, L>(tw, twg);
   batched_copy<8, T>(
       L * nz, [&](int e) { return src[e]; },
       [&](int e, cplx<T> v) {

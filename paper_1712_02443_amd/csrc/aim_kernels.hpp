@@ -20,6 +20,7 @@ struct ProjArgs {
   const int* node_ptr;
   const int* node_ent;
   const int* node_n;
+  const void* zero;  // one zero complex value (read for absent neighbours)
 };
 
 // FFT lengths L = L1 L2 with register-DFT (four-step) passes

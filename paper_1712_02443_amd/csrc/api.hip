@@ -162,6 +162,7 @@ static ProjArgs proj_args(aim_op* op, int R) {
   a.node_ptr = op->node_ptr;
   a.node_ent = op->node_ent;
   a.node_n = op->node_n;
+  a.zero = op->zero;
   return a;
 }
 
