@@ -365,6 +365,28 @@ __global__ void __launch_bounds__(kBS) k_next_span(const cplx<Tb>* __restrict__ 
   if (threadIdx.x == 0) part[int64_t(r) * nch + c] = nn;
 }
 
+// Thread partial of sum_c p[c * stride] over c = tid, tid + kBS, ... (in that order),
+// loads issued in batches of 16 so they are in flight together.
+__device__ __forceinline__ void thread_partials(const double* __restrict__ p, int nch, int stride, double& a,
+                                                double* b) {
+  constexpr int kU = 16;
+  for (int c0 = 0; c0 < nch; c0 += kU * kBS) {
+    double va[kU], vb[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int c = min(c0 + u * kBS + int(threadIdx.x), nch - 1);
+      va[u] = p[int64_t(c) * stride];
+      if (b) vb[u] = p[int64_t(c) * stride + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const bool in = c0 + u * kBS + int(threadIdx.x) < nch;
+      a += in ? va[u] : 0.0;
+      if (b) *b += in ? vb[u] : 0.0;
+    }
+  }
+}
+
 // h[r][i] (+)= sum_c part ; one block per (r, i), fixed summation order
 __global__ void __launch_bounds__(kBS) k_reduce_dots(const double* __restrict__ part, cplx<double>* h, int nch, int nv,
                                                      int R, int ldh, int accumulate) {
@@ -374,11 +396,7 @@ __global__ void __launch_bounds__(kBS) k_reduce_dots(const double* __restrict__ 
   const int r = t / nv, i = t - r * nv;
   const double* p = part + int64_t(t) * nch * 2;
   double a = 0, b = 0;
-#pragma unroll 4
-  for (int c = threadIdx.x; c < nch; c += kBS) {
-    a += p[2 * c];
-    b += p[2 * c + 1];
-  }
+  thread_partials(p, nch, 2, a, &b);
   block_sum2(a, b, sh);
   if (threadIdx.x == 0) {
     cplx<double>& o = h[int64_t(r) * ldh + i];
@@ -394,7 +412,9 @@ __global__ void __launch_bounds__(kBS) k_reduce_dots(const double* __restrict__ 
 
 // Per right-hand side: p_i = s_i pq_i, new Gram column S_ij = s_i s_j pq_{nv+i}
 // (i <= j), c = 2 p - S p.  hcol <- c (the Hessenberg column above the diagonal),
-// cr <- s_i c_i (coefficients of the stored u_i).  S: [R][m+1][m+1] column-major.
+// cr <- s_i c_i (coefficients of the stored u_i).  S: [R][m+1][m+1] column-major,
+// Hermitian, so (S p)_i = sum_k conj(S_ki) p_k reads column i contiguously; one wave
+// per row i, lanes over k, a fixed-order lane sum.
 __global__ void __launch_bounds__(kBS) k_gram(const cplx<double>* __restrict__ pq, int ldpq, cplx<double>* S,
                                               const double* __restrict__ sc, cplx<double>* __restrict__ hcol,
                                               cplx<double>* __restrict__ cr, int m, int j, int R) {
@@ -414,21 +434,34 @@ __global__ void __launch_bounds__(kBS) k_gram(const cplx<double>* __restrict__ p
   for (int i = threadIdx.x; i < nv; i += blockDim.x) {
     Sr[i + int64_t(j) * ld] = qs[i];
     Sr[j + int64_t(i) * ld] = cmk<double>(qs[i].re, -qs[i].im);
-    // (S p)_i, entries of column / row j taken from qs (written just now)
-    cplx<double> acc = cmk<double>(0, 0);
-    for (int k = 0; k < nv; ++k) {
-      cplx<double> sik;
-      if (k == j)
-        sik = qs[i];
-      else if (i == j)
-        sik = cmk<double>(qs[k].re, -qs[k].im);
-      else
-        sik = Sr[i + int64_t(k) * ld];
-      cfma(acc, sik, ps[k]);
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = wave; i < nv; i += kBS / 64) {
+    // S_ki for k < nv: column i of the stored matrix, except row j (conj q_i) and,
+    // for i = j, the new column (q_k); both come from qs
+    double a = 0, b = 0;
+    for (int k0 = 0; k0 < nv; k0 += 64) {
+      const int k = k0 + lane;
+      if (k < nv) {
+        cplx<double> ski;
+        if (i == j)
+          ski = qs[k];
+        else if (k == j)
+          ski = cmk<double>(qs[i].re, -qs[i].im);
+        else
+          ski = Sr[k + int64_t(i) * ld];
+        // conj(S_ki) p_k
+        a += ski.re * ps[k].re + ski.im * ps[k].im;
+        b += ski.re * ps[k].im - ski.im * ps[k].re;
+      }
     }
-    const cplx<double> cv = cmk<double>(2 * ps[i].re - acc.re, 2 * ps[i].im - acc.im);
-    hcol[int64_t(r) * ld + i] = cv;
-    cr[int64_t(r) * ld + i] = cmk<double>(cv.re * s[i], cv.im * s[i]);
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) {
+      const cplx<double> cv = cmk<double>(2 * ps[i].re - a, 2 * ps[i].im - b);
+      hcol[int64_t(r) * ld + i] = cv;
+      cr[int64_t(r) * ld + i] = cmk<double>(cv.re * s[i], cv.im * s[i]);
+    }
   }
 }
 
@@ -452,8 +485,7 @@ __global__ void __launch_bounds__(kBS) k_finish_step(const double* __restrict__ 
   const int r = blockIdx.x;
   if (r >= R) return;
   double sum = 0, dummy = 0;
-#pragma unroll 4
-  for (int c = threadIdx.x; c < nch; c += kBS) sum += part[int64_t(r) * nch + c];
+  thread_partials(part + int64_t(r) * nch, nch, 1, sum, nullptr);
   block_sum2(sum, dummy, sh);
   if (threadIdx.x == 0) {
     const double beta = sqrt(sum);
@@ -643,10 +675,18 @@ int launch_step(int pass, const cplx<Tb>* V, const cplx<float>* wlo, const cplx<
     launch_step_n<Tb, 8>(pass, V, wlo, w, sc, ldsc, cr, ldc, unext, part, n, nv, R, s);
   else if (nv <= 16)
     launch_step_n<Tb, 16>(pass, V, wlo, w, sc, ldsc, cr, ldc, unext, part, n, nv, R, s);
+  else if (nv <= 24)
+    launch_step_n<Tb, 24>(pass, V, wlo, w, sc, ldsc, cr, ldc, unext, part, n, nv, R, s);
   else if (nv <= 32 || kSpanMax<Tb> <= 32)
     launch_step_n<Tb, 32>(pass, V, wlo, w, sc, ldsc, cr, ldc, unext, part, n, nv, R, s);
-  else if constexpr (kSpanMax<Tb> >= 64)
-    launch_step_n<Tb, 64>(pass, V, wlo, w, sc, ldsc, cr, ldc, unext, part, n, nv, R, s);
+  else if constexpr (kSpanMax<Tb> >= 64) {
+    if (nv <= 40)
+      launch_step_n<Tb, 40>(pass, V, wlo, w, sc, ldsc, cr, ldc, unext, part, n, nv, R, s);
+    else if (nv <= 48)
+      launch_step_n<Tb, 48>(pass, V, wlo, w, sc, ldsc, cr, ldc, unext, part, n, nv, R, s);
+    else
+      launch_step_n<Tb, 64>(pass, V, wlo, w, sc, ldsc, cr, ldc, unext, part, n, nv, R, s);
+  }
   return int(nblk(n, kBS));
 }
 
