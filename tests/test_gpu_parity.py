@@ -258,3 +258,29 @@ def test_full_size_sampled_rows(torch, prec):
     rows = np.concatenate([rng.choice(wl.n_unknowns, 48, replace=False), [0, wl.n_unknowns - 1]])
     ref = o.matvec_rows(x, rows)
     assert rel(y[rows], ref) < TOL[prec]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("idx", [2, 4])
+def test_full_size_multi_rhs_sampled_rows(torch, idx):
+    """The two multi-RHS workloads at full size, all right-hand sides in one launch:
+    16 x 16 plates of three kinds with 64 RHS (73,728 unknowns each, 200 x 200 FFT) and
+    the 64 x 64 two-kind array with 8 RHS (2,654,208 unknowns each, 800 x 800 FFT).
+    First and last RHS checked on sampled rows computed by the oracle, both precisions."""
+    from paper_1712_02443_amd import AimOperator
+    wl = make_workload(idx)
+    say(f"full-size {wl.name}: {wl.nrhs} rhs x {wl.n_unknowns}")
+    op = AimOperator.from_workload(wl)
+    op.set_macromodels(wl.macromodels())
+    op.set_dmatrix(*wl.d_matrix())
+    o = OracleOperator(wl)
+    X = wl.test_vectors()
+    rng = np.random.default_rng(13)
+    rows = np.concatenate([rng.choice(wl.n_unknowns, 30, replace=False), [0, wl.n_unknowns - 1]])
+    refs = {r: o.matvec_rows(X[r], rows) for r in (0, wl.nrhs - 1)}
+    for prec in (0, 1):
+        Y = op.matvec(to_dev(torch, X, prec), precision=prec)
+        for r, ref in refs.items():
+            assert rel(to_host(Y[r])[rows], ref) < TOL[prec]
+        del Y
+    op.close()
