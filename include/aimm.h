@@ -99,12 +99,15 @@ typedef struct {
   int64_t device_bytes;        /* device memory held by the op */
   int32_t paths;               /* kernels in use: AIM_PATH_FFT_REGISTER (FFT passes of
                                   in-register DFTs, else radix stages), AIM_PATH_NEAR_MFMA
-                                  (near field on the matrix cores, else sparse rows);
+                                  (near field on the matrix cores, else sparse rows),
+                                  AIM_PATH_GEMM_BF16X3 (mixed-path macromodel product as
+                                  split-BF16 MFMA with FP32 accumulation, else FP32 MFMA);
                                   0 for host-only ops */
 } aim_info;
 
 #define AIM_PATH_FFT_REGISTER 1
 #define AIM_PATH_NEAR_MFMA 2
+#define AIM_PATH_GEMM_BF16X3 4
 
 /* Build the AIM operator of section V for the array: stencils, projection and
  * interpolation weights, FFT plan and Green's-function spectrum (on the device),

@@ -833,6 +833,114 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const cplx<float>* __restrict_
   gemm_reduce_store<float>(part, U, colbase, N, a.ne, i0);
 }
 
+// ---- split-BF16 macromodel product (the mixed path's bf16 matrix cores) -------------
+// Every FP32 value v is carried as three bfloat16 terms v = h + m + l (h = bf16(v),
+// m = bf16(v - h), l = bf16(v - h - m); each difference is exact in FP32), and a real
+// product uses the six bf16 products h.h + h.m + m.h + h.l + l.h + m.m, accumulated
+// in FP32 by v_mfma_f32_32x32x16_bf16 (the dropped terms are below 2^-24 relative).
+// Complex steps take three real products as in the FP32 kernel.  M is pre-split on
+// the host into 9 planes (h, m, l of re, im, re + im) laid out [plane][k / 8][row][8]
+// so a lane's 8 consecutive k of one row are one 16-byte load; X is split on the fly
+// (8 consecutive k of one column, 64 contiguous bytes, per lane).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split3(float v, __bf16& h, __bf16& m, __bf16& l) {
+  h = __bf16(v);
+  const float r1 = v - float(h);
+  m = __bf16(r1);
+  l = __bf16(r1 - float(m));
+}
+
+__global__ void __launch_bounds__(256) k_gemm_bf16x3(const u32x4* __restrict__ Mb, const cplx<float>* __restrict__ X,
+                                                     cplx<float>* __restrict__ U, GemmArgs a) {
+  __shared__ cplx<float> part[4 * kGemmRows * (kGemmCols + 1)];
+  __shared__ int cols[kGemmCols];
+  __shared__ int64_t colbase[kGemmCols];
+  int t;
+  gemm_tile_setup(a, t, cols, colbase);
+  __syncthreads();
+  const int N = a.N, i0 = blockIdx.y * kGemmRows;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = lane & 31, hk = lane >> 5;
+  const int ir = min(i0 + i, N - 1);  // rows past N: any valid row, outputs discarded
+  const int colj = max(cols[lane & 31], 0);
+  const int kq = a.Kq, kb = w * kq, ke = kb + kq;
+  const int KB = a.Krows / 8;
+  const u32x4* Mt = Mb + int64_t(t) * 9 * KB * N;
+  const cplx<float>* xc = X + int64_t(colj) * N;
+  // lane's 8 k of the chunk at k0: A rows ir, k0 + 8 hk .. + 7 (9 planes); B column colj
+  auto load_a = [&](int k0, u32x4* av) {
+#pragma unroll
+    for (int p = 0; p < 9; ++p) av[p] = Mt[(int64_t(p) * KB + (k0 >> 3) + hk) * N + ir];
+  };
+  auto load_b = [&](int k0, cplx<float>* bv) {
+    const int kk = k0 + 8 * hk;
+    const cplx<float>* src = xc + (kk + 8 <= N ? kk : 0);  // past N: any finite values (M rows are zero)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) bv[u] = src[u];
+  };
+  f32x16 accRR = {}, accII = {}, accSS = {};
+  auto mma6 = [](f32x16 acc, const bf16x8* a3, const bf16x8* b3) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[0], b3[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[0], b3[1], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[1], b3[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[0], b3[2], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[2], b3[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[1], b3[1], acc, 0, 0, 0);
+    return acc;
+  };
+  u32x4 ca[9], na[9];
+  cplx<float> cb[8], nb[8];
+  load_a(kb, ca);
+  load_b(kb, cb);
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    if (k0 + 16 < ke) {
+      load_a(k0 + 16, na);
+      load_b(k0 + 16, nb);
+    }
+    bf16x8 br[3], bi[3], bs[3];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      __bf16 h, m, l;
+      split3(cb[u].re, h, m, l);
+      br[0][u] = h;
+      br[1][u] = m;
+      br[2][u] = l;
+      split3(cb[u].im, h, m, l);
+      bi[0][u] = h;
+      bi[1][u] = m;
+      bi[2][u] = l;
+      split3(cb[u].re + cb[u].im, h, m, l);
+      bs[0][u] = h;
+      bs[1][u] = m;
+      bs[2][u] = l;
+    }
+    bf16x8 ar[3], ai[3], as[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      ar[p] = __builtin_bit_cast(bf16x8, ca[p]);
+      ai[p] = __builtin_bit_cast(bf16x8, ca[3 + p]);
+      as[p] = __builtin_bit_cast(bf16x8, ca[6 + p]);
+    }
+    accRR = mma6(accRR, ar, br);
+    accII = mma6(accII, ai, bi);
+    accSS = mma6(accSS, as, bs);
+#pragma unroll
+    for (int p = 0; p < 9; ++p) ca[p] = na[p];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cb[u] = nb[u];
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);  // 32 x 32 MFMA output row
+    part[(w * kGemmRows + row) * (kGemmCols + 1) + (lane & 31)] =
+        cmk<float>(accRR[r] - accII[r], accSS[r] - accRR[r] - accII[r]);
+  }
+  __syncthreads();
+  gemm_reduce_store<float>(part, U, colbase, N, a.ne, i0);
+}
+
 __global__ void __launch_bounds__(256) k_gemm_f64(const cplx<double>* __restrict__ M,
                                                   const cplx<double>* __restrict__ X, cplx<double>* __restrict__ U,
                                                   GemmArgs a) {
@@ -1106,12 +1214,17 @@ hipError_t launch_macro(const cplx<T>* M, const cplx<T>* X, cplx<T>* U, const Ge
   const int tiles = a.tile_start[a.n_types];  // host copy of the tile prefix sums
   if (tiles == 0) return hipSuccess;
   const dim3 g(tiles, (a.N + kGemmRows - 1) / kGemmRows), b(256);
-  if constexpr (sizeof(T) == sizeof(float))
-    hipLaunchKernelGGL(k_gemm_f32, g, b, 0, s, reinterpret_cast<const cplx<float>*>(M),
-                       reinterpret_cast<const cplx<float>*>(X), reinterpret_cast<cplx<float>*>(U), a);
-  else
+  if constexpr (sizeof(T) == sizeof(float)) {
+    if (a.Mb)
+      hipLaunchKernelGGL(k_gemm_bf16x3, g, b, 0, s, static_cast<const u32x4*>(a.Mb),
+                         reinterpret_cast<const cplx<float>*>(X), reinterpret_cast<cplx<float>*>(U), a);
+    else
+      hipLaunchKernelGGL(k_gemm_f32, g, b, 0, s, reinterpret_cast<const cplx<float>*>(M),
+                         reinterpret_cast<const cplx<float>*>(X), reinterpret_cast<cplx<float>*>(U), a);
+  } else {
     hipLaunchKernelGGL(k_gemm_f64, g, b, 0, s, reinterpret_cast<const cplx<double>*>(M),
                        reinterpret_cast<const cplx<double>*>(X), reinterpret_cast<cplx<double>*>(U), a);
+  }
   return hipGetLastError();
 }
 

@@ -89,6 +89,7 @@ inline int gemm_krows(int N) { return 4 * gemm_kq(N) + kGemmKTail; }
 struct GemmArgs {
   int N, R, n_types, ne;
   int Kq, Krows;
+  const void* Mb;  // split-BF16 planes of M (FP32 path), or null for the FP32 MFMA kernel
   int tile_start[kMaxTypes + 1];
   int type_count[kMaxTypes];
   int col_start[kMaxTypes];

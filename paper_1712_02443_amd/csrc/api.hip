@@ -236,6 +236,7 @@ static GemmArgs gemm_args(aim_op* op, int R) {
   a.n_types = op->n_types;
   a.Kq = gemm_kq(op->N);
   a.Krows = gemm_krows(op->N);
+  a.Mb = op->gemm_bf16 ? op->Mb : nullptr;
   a.col_list = op->col_list;
   a.tile_start[0] = 0;
   for (int t = 0; t < op->n_types; ++t) {
@@ -456,6 +457,9 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
     if (const char* env = std::getenv("AIMM_FFT4")) op->fft4 = op->fft4 && std::atoi(env) != 0;
     // the matrix-core kernel stages a group's columns in LDS
     if (size_t(st.grp_max_cols) * sizeof(int) > 32768) op->near_mfma = false;
+    // split-BF16 macromodel product in the mixed path (AIMM_GEMM=fp32 selects the FP32 kernel)
+    op->gemm_bf16 = op->N % 8 == 0;
+    if (const char* env = std::getenv("AIMM_GEMM")) op->gemm_bf16 = op->gemm_bf16 && std::strcmp(env, "fp32") != 0;
     if (const char* env = std::getenv("AIMM_INTERP_TILE")) std::sscanf(env, "%dx%d", &op->interp_tx, &op->interp_ty);
     // macromodel column lists, r-major within each kind
     op->type_count.assign(a.n_types, 0);
@@ -526,6 +530,27 @@ int aim_build_host(const aim_surface* surface, const aim_array* array, aim_op** 
   return build_op(surface, array, out, false);
 }
 
+// bf16 round-to-nearest-even of a finite float, and v = h + m + l in bf16 terms (each
+// remainder is exact in FP32)
+static uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+static float bf16_to_float(uint16_t b) {
+  const uint32_t u = uint32_t(b) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+static void split_bf16(float v, uint16_t out[3]) {
+  out[0] = bf16_rne(v);
+  const float r1 = v - bf16_to_float(out[0]);
+  out[1] = bf16_rne(r1);
+  out[2] = bf16_rne(r1 - bf16_to_float(out[1]));
+}
+
 int aim_set_macromodels(aim_op* op, const double* M) {
   if (!op || !M) {
     set_error("op and M must not be NULL");
@@ -555,6 +580,25 @@ int aim_set_macromodels(aim_op* op, const double* M) {
       }
     AIM_HIP(hipMemcpy(op->p64.M, m64.data(), n * sizeof(cplx<double>), hipMemcpyHostToDevice));
     AIM_HIP(hipMemcpy(op->p32.M, m32.data(), n * sizeof(cplx<float>), hipMemcpyHostToDevice));
+    if (op->N % 8 == 0) {
+      // split-BF16 planes: per kind, [h, m, l of re; of im; of re + im][k / 8][row][k % 8]
+      const size_t KB = kr / 8, per = 9 * KB * N * 8;
+      std::vector<uint16_t> mb(size_t(op->n_types) * per, 0);
+      for (size_t t = 0; t < size_t(op->n_types); ++t)
+        for (size_t k = 0; k < kr; ++k)
+          for (size_t i = 0; i < N; ++i) {
+            const cplx<float> v = m32[t * kr * N + k * N + i];
+            const float comp[3] = {v.re, v.im, v.re + v.im};
+            for (int c = 0; c < 3; ++c) {
+              uint16_t part3[3];
+              split_bf16(comp[c], part3);
+              for (int q = 0; q < 3; ++q)
+                mb[t * per + ((size_t(3 * c + q) * KB + k / 8) * N + i) * 8 + k % 8] = part3[q];
+            }
+          }
+      if (!op->Mb) op->Mb = op->mem.alloc<uint16_t>(mb.size());
+      AIM_HIP(hipMemcpy(op->Mb, mb.data(), mb.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+    }
   } catch (const std::bad_alloc&) {
     set_error("device allocation failed");
     return AIM_ENOMEM;
@@ -782,7 +826,8 @@ int aim_get_info(const aim_op* op, aim_info* info) {
   info->near_nnz = int64_t(op->st.near_val.size());
   info->d_nnz = op->d_nnz;
   info->device_bytes = int64_t(op->mem.bytes);
-  info->paths = op->device_ready ? ((op->fft4 ? AIM_PATH_FFT_REGISTER : 0) | (op->near_mfma ? AIM_PATH_NEAR_MFMA : 0))
+  info->paths = op->device_ready ? ((op->fft4 ? AIM_PATH_FFT_REGISTER : 0) | (op->near_mfma ? AIM_PATH_NEAR_MFMA : 0) |
+                                    (op->gemm_bf16 ? AIM_PATH_GEMM_BF16X3 : 0))
                                  : 0;
   return AIM_OK;
 }
@@ -832,6 +877,7 @@ size_t aim_footprint_bytes(const aim_surface* surface, const aim_array* array, i
   b += R * 4 * nx * Ly * ez * 16;                    // spectrum pass
   b += (Lx / 2 + 1) * (Ly / 2 + 1) * ez * 24;        // kernel spectrum, both precisions
   b += size_t(array->n_types) * N * N * 24;          // macromodels
+  b += size_t(array->n_types) * 9 * (4 * ((N + 63) / 64 * 16) + 16) * N * 2;  // their split-BF16 planes
   b += N * 600 * 28 + N * q * q * q * 4 * 24;        // near field (upper estimate) and weights
   const size_t vec = precision == AIM_FP64 ? 16 : 8;
   b += size_t(restart + 1) * size_t(nrhs) * n * vec;  // Krylov basis

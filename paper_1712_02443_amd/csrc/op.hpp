@@ -109,6 +109,8 @@ struct aim_op {
   aimm::cplx<double>* zero = nullptr;  // one zero value (16 bytes; also read as complex64)
   bool near_mfma = true;
   bool fft4 = false;  // register-DFT FFT passes
+  bool gemm_bf16 = false;  // mixed-path macromodel product on the bf16 matrix cores (split in three)
+  void* Mb = nullptr;      // [n_types][9 planes][Krows / 8][N][8] bf16
   int interp_tx = 0, interp_ty = 0;  // 0 = automatic  // [n_off][2] lattice offsets of the near-field blocks
   int *nbr = nullptr, *d_colT = nullptr, *rev_x = nullptr, *rev_y = nullptr, *col_list = nullptr;
   aimm::PrecData<double> p64;

@@ -148,6 +148,26 @@ def test_radix_stage_fft_path(torch, case, monkeypatch):
     op.close()
 
 
+@pytest.mark.parametrize("case", [CASES[1], CASES[2]])
+def test_fp32_gemm_path(torch, case, monkeypatch):
+    """The mixed path's FP32-MFMA macromodel product (the alternative to the split-BF16
+    one) against the oracle; the default op must be on the split-BF16 kernel."""
+    from paper_1712_02443_amd import AIM_MIXED, AimOperator
+    wl, op_fast, o = make_pair(torch, case[0], **case[1])
+    assert op_fast.info()["paths"] & 4, "split-BF16 macromodel product expected"
+    monkeypatch.setenv("AIMM_GEMM", "fp32")
+    op = AimOperator.from_workload(wl)
+    op.set_macromodels(wl.macromodels())
+    op.set_dmatrix(*wl.d_matrix())
+    assert not op.info()["paths"] & 4
+    say(f"fp32 gemm {wl.name}")
+    X = wl.test_vectors()
+    U = to_host(op.macro_apply(to_dev(torch, X, AIM_MIXED), precision=AIM_MIXED))
+    assert rel(U, np.stack([o.macro_apply(x) for x in X])) < TOL[1]
+    assert rel(to_host(op.matvec(to_dev(torch, X, AIM_MIXED), precision=AIM_MIXED)), o.matvec(X)) < TOL[1]
+    op.close()
+
+
 def test_product_is_deterministic_and_batch_invariant(torch):
     wl, op, o = make_pair(torch, 2, px=5, py=3, nrhs=3)
     say("determinism")
