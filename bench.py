@@ -30,7 +30,7 @@ COPY_BYTES = 536870912  # the plain device copy that calibrates the byte counter
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_jc32x32_fp32_product.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1712_02443_amd", "csrc", "aim_kernels.hip")
 # device kernel name prefixes (FP32 product) -> per-kernel keys of this benchmark
-KERNEL_KEYS = [("k_gemm_f32", "macro_gemm"), ("k_project<float>", "project"), ("k_fft4_y_fwd<float", "fft_y_fwd"),
+KERNEL_KEYS = [("k_gemm_bf16x3", "macro_gemm"), ("k_gemm_f32", "macro_gemm"), ("k_project<float>", "project"), ("k_fft4_y_fwd<float", "fft_y_fwd"),
                ("k_fft_y_fwd<float>", "fft_y_fwd"), ("k_fft4_x<float", "fft_x_conv"), ("k_fft_x<float, 0>", "fft_x_conv"),
                ("k_fft4_y_inv<float", "fft_y_inv"), ("k_fft_y_inv<float>", "fft_y_inv"),
                ("k_near_mfma<float>", "near_field"), ("k_near<float>", "near_field"), ("k_interp<float, 0", "interp_d")]
