@@ -10,8 +10,9 @@ One step = one GMRES(50) solve to 1e-6 relative residual in mixed precision
 (complex FP32 products and basis, FP64 Gram-Schmidt sums, Hessenberg, Givens and
 a FP64 residual product at every restart).  `value` = AIM matrix-vector products
 per second over the timed solves (every product counts, FP64 restart products
-included).  The FP64 solve, the standalone products, per-kernel times and the
-oracle's CPU rate are reported beside it.
+included).  The FP64 solve, the same solves right-preconditioned with the per-kind
+block-Jacobi inverses ("block_jacobi"), the standalone products, per-kernel times
+and the oracle's CPU rate are reported beside it.
 """
 from __future__ import annotations
 
@@ -157,6 +158,7 @@ def main() -> int:
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solves")
+    ap.add_argument("--no-precond", action="store_true", help="skip the block-Jacobi preconditioned solves")
     ap.add_argument("--profile-products", type=int, default=0,
                     help="only run this many FP32 and FP64 products and a 512 MiB device copy "
                          "(the copy calibrates hardware byte counters), then exit")
@@ -175,7 +177,7 @@ def main() -> int:
     import numpy as np
     import torch
 
-    from paper_1712_02443_amd import AIM_FP64, AIM_MIXED, AimOperator
+    from paper_1712_02443_amd import AIM_FP64, AIM_MIXED, AIM_PRECOND_BLOCK_JACOBI, AimOperator
     from synth import make_workload
 
     if not torch.cuda.is_available():
@@ -253,6 +255,39 @@ def main() -> int:
         out["fp64_true_relres"] = st64["true_relres"]
         out["mixed_vs_fp64_solve_speedup"] = (e64 / args.steps) / (elapsed / args.steps)
         print(f"[bench] fp64: {out['fp64_solve_ms']:.2f} ms/solve, {st64}", file=sys.stderr, flush=True)
+
+    if not args.no_precond:
+        # the same solves right-preconditioned with the per-kind block-Jacobi inverses
+        t = time.perf_counter()
+        op.build_preconditioner()
+        torch.cuda.synchronize()
+        bj = {"setup_s": time.perf_counter() - t}
+        pkw = dict(solve_kw, precond=AIM_PRECOND_BLOCK_JACOBI)
+
+        def psolve(prec):
+            x, st, code = op.gmres(b, precision=prec, **pkw)
+            return st[0], code
+
+        for prec, tag in ((AIM_MIXED, "mixed"), (AIM_FP64, "fp64")):
+            if prec == AIM_FP64 and args.no_fp64:
+                continue
+            psolve(prec)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.steps):
+                stp, cp = psolve(prec)
+            torch.cuda.synchronize()
+            ep = time.perf_counter() - t
+            bj[f"{tag}_solve_ms"] = ep / args.steps * 1e3
+            bj[f"{tag}_iters"] = stp["iters"]
+            bj[f"{tag}_matvecs_per_solve"] = stp["matvecs"]
+            bj[f"{tag}_true_relres"] = stp["true_relres"]
+            bj[f"{tag}_converged"] = bool(stp["converged"])
+        bj["mixed_speedup_vs_unpreconditioned_mixed"] = (elapsed / args.steps * 1e3) / bj["mixed_solve_ms"]
+        if "fp64_solve_ms" in bj:
+            bj["mixed_vs_fp64_solve_speedup"] = bj["fp64_solve_ms"] / bj["mixed_solve_ms"]
+        out["block_jacobi"] = bj
+        print(f"[bench] block-Jacobi: {bj}", file=sys.stderr, flush=True)
 
     # standalone products
     x64 = torch.from_numpy(wl.test_vectors(1)).to("cuda")

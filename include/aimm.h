@@ -117,17 +117,21 @@ typedef struct {
 int aim_build_grid(const aim_surface* surface, const aim_array* array, aim_op** out);
 
 /* The host part of aim_build_grid alone: stencils, weights and the pre-corrected
- * near field, with no device call.  The op serves aim_get_info and aim_get_near;
- * every device entry point returns AIM_ESTATE on it.  For inspection and tests on
- * hosts without a GPU. */
+ * near field, with no device call.  The op serves aim_get_info, aim_get_near and
+ * the host parts of aim_set_macromodels, aim_set_dmatrix, aim_build_preconditioner
+ * and aim_get_preconditioner; every device entry point returns AIM_ESTATE on it.
+ * For inspection and tests on hosts without a GPU. */
 int aim_build_host(const aim_surface* surface, const aim_array* array, aim_op** out);
 
 /* Per-kind block M_t = T_t A_t^-1 B_t (section III, eq. Tm1 and eq. JABE), host
- * complex128 [n_types][N][N], column-major within each block.  Copied. */
+ * complex128 [n_types][N][N], column-major within each block.  Copied (to the
+ * device, and kept on the host for aim_build_preconditioner; a host-only op keeps
+ * the host copy only).  May be called again to replace the blocks. */
 int aim_set_macromodels(aim_op* op, const double* M);
 
 /* The sparse block D_m (section IV) shared by all elements, as host coordinate
- * lists: rows[nnz], cols[nnz] in [0, N), vals complex128 [nnz].  Copied. */
+ * lists: rows[nnz], cols[nnz] in [0, N), vals complex128 [nnz].  Copied (host copy
+ * kept as for the macromodels).  Set once per op (AIM_ESTATE on a second call). */
 int aim_set_dmatrix(aim_op* op, int64_t nnz, const int32_t* rows, const int32_t* cols,
                     const double* vals);
 
@@ -175,8 +179,17 @@ typedef struct {
   int32_t check_every;  /* most iterations between host checks of the stop flags
                            (>= 1); checks come earlier where the residual estimate
                            predicts convergence.  Results do not depend on it. */
+  int32_t precond;      /* aim_precond: AIM_PRECOND_NONE, or AIM_PRECOND_BLOCK_JACOBI
+                           (right preconditioning, A P z = b, x = P z, with the
+                           blocks of aim_build_preconditioner; the residual that
+                           tol and the stats refer to is still b - A x) */
   double tol;           /* relative residual target ||b - A x|| / ||b|| */
 } gmres_opts;
+
+enum aim_precond {
+  AIM_PRECOND_NONE = 0,
+  AIM_PRECOND_BLOCK_JACOBI = 1
+};
 
 typedef struct {
   int32_t iters;        /* inner iterations */
@@ -194,6 +207,26 @@ typedef struct {
  * Krylov basis on first use and keeps it with the op. */
 int gmres_solve(aim_op* op, const void* b, void* x, int32_t nrhs, const gmres_opts* opts,
                 gmres_stat* stats, void* stream);
+
+/* Block-Jacobi preconditioner of the final system (section IV eq. finalsystem;
+ * the paper preconditions GMRES with an incomplete factorisation of the near-field
+ * matrix, section VI).  The diagonal block of element m is D - G_self M_t(m), where
+ * G_self is the AIM operator on one element's own RWG functions (the grid part on
+ * every pair plus the pre-corrected near field of lattice offset (0, 0)); it is the
+ * same for all elements of one kind, so the library computes one FP64 inverse
+ * P_t = (D - G_self M_t)^-1 per kind on the host (partially pivoted LU) and keeps it
+ * on the device in the layouts of M_t.  Needs aim_set_macromodels and
+ * aim_set_dmatrix first (AIM_ESTATE otherwise); aim_set_macromodels makes it stale
+ * until it is built again.  AIM_EINVAL if a block is singular.  Works on host-only
+ * ops too (host copy only).  Runs for seconds on large N (O(N^3) per kind). */
+int aim_build_preconditioner(aim_op* op);
+
+/* Copy of the blocks P_t: host complex128 [n_types][N][N], column-major. */
+int aim_get_preconditioner(const aim_op* op, double* P);
+
+/* y = blockdiag(P_t(m)) x for nrhs right-hand sides; x, y: device, element-major,
+ * must not alias.  The grouped product of macro_apply with the blocks P_t. */
+int precond_apply(aim_op* op, const void* x, void* y, int32_t nrhs, int32_t precision, void* stream);
 
 /* Sizes of the op (host only, no device work). */
 int aim_get_info(const aim_op* op, aim_info* info);

@@ -14,7 +14,8 @@ What it computes, each function citing the passage of the paper it follows:
     near-field matrix with its pre-correction;
   * the final-system product (D - G T A^-1 B) Y (section V eq. MV_product1),
     with T A^-1 B given as the per-type block M_t (section III);
-  * GMRES(m) on the final system (section V, eq. finalsystem);
+  * GMRES(m) on the final system (section V, eq. finalsystem), optionally right
+    preconditioned with the per-kind block-Jacobi inverse of the diagonal blocks;
   * the plane-wave excitation vector (section IV eq. V1).
 
 Floating point is IEEE double throughout; numpy / scipy supply matmul and FFT

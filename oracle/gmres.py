@@ -1,10 +1,13 @@
 """Restarted GMRES (Saad and Schultz 1986) on the final system (section V eq. finalsystem).
 
 The paper names GMRES and nothing more of its setup; the readings here: x0 = 0,
-no preconditioner, modified Gram-Schmidt Arnoldi, Givens rotations for the
-least-squares update, and convergence judged on the true residual
-||b - A x|| / ||b|| recomputed in FP64 at every restart; every right-hand side
-is solved independently.
+modified Gram-Schmidt Arnoldi, Givens rotations for the least-squares update, and
+convergence judged on the true residual ||b - A x|| / ||b|| recomputed in FP64 at
+every restart; every right-hand side is solved independently.  Unpreconditioned by
+default; with `precond` (a callable applying P) it is right preconditioned (Saad,
+Iterative Methods for Sparse Linear Systems, 2nd ed., sec. 9.3.2): the Krylov space
+is built from v -> A P v, the iterate is updated by x += P (V y), and the residual
+that stops it is still b - A x of the unpreconditioned system.
 """
 from __future__ import annotations
 
@@ -12,8 +15,9 @@ import numpy as np
 
 
 def gmres(matvec, b: np.ndarray, restart: int = 50, tol: float = 1e-6, max_iters: int = 1000,
-          x0: np.ndarray | None = None):
+          x0: np.ndarray | None = None, precond=None):
     """Solve A x = b for one vector.  Returns (x, info) with iters, restarts, relres, history."""
+    P = (lambda v: v) if precond is None else precond
     n = b.shape[0]
     x = np.zeros(n, dtype=np.complex128) if x0 is None else x0.astype(np.complex128).copy()
     bnorm = np.linalg.norm(b)
@@ -39,7 +43,7 @@ def gmres(matvec, b: np.ndarray, restart: int = 50, tol: float = 1e-6, max_iters
         V[0] = r / beta
         j_used = 0
         for j in range(restart):
-            w = matvec(V[j])
+            w = matvec(P(V[j]))
             for i in range(j + 1):
                 H[i, j] = np.vdot(V[i], w)
                 w = w - H[i, j] * V[i]
@@ -65,7 +69,7 @@ def gmres(matvec, b: np.ndarray, restart: int = 50, tol: float = 1e-6, max_iters
             if abs(g[j + 1]) / bnorm <= tol or iters >= max_iters:
                 break
         y = np.linalg.solve(np.triu(H[:j_used, :j_used]), g[:j_used])
-        x = x + V[:j_used].T @ y
+        x = x + P(V[:j_used].T @ y)
         restarts += 1
         r = b - matvec(x)
         beta = np.linalg.norm(r)

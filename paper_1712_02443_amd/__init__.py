@@ -13,11 +13,11 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (AIM_FAR_ONLY, AIM_FP64, AIM_FULL, AIM_G_ONLY, AIM_MIXED, AimError, GmresOpts, GmresStat,
-                   check, load)
+from ._lib import (AIM_FAR_ONLY, AIM_FP64, AIM_FULL, AIM_G_ONLY, AIM_MIXED, AIM_PRECOND_BLOCK_JACOBI,
+                   AIM_PRECOND_NONE, AimError, GmresOpts, GmresStat, check, load)
 
-__all__ = ["AimOperator", "AIM_FP64", "AIM_MIXED", "AIM_FULL", "AIM_G_ONLY", "AIM_FAR_ONLY", "AimError",
-           "footprint_bytes", "load"]
+__all__ = ["AimOperator", "AIM_FP64", "AIM_MIXED", "AIM_FULL", "AIM_G_ONLY", "AIM_FAR_ONLY",
+           "AIM_PRECOND_NONE", "AIM_PRECOND_BLOCK_JACOBI", "AimError", "footprint_bytes", "load"]
 
 
 def _stream(torch, stream):
@@ -89,6 +89,24 @@ class AimOperator:
         v = np.ascontiguousarray(vals, dtype=np.complex128)
         check(self.lib.aim_set_dmatrix(self._op, r.shape[0], r.ctypes.data_as(_lib._i32p),
                                        c.ctypes.data_as(_lib._i32p), v.view(np.float64).ctypes.data_as(_lib._f64p)))
+
+    def build_preconditioner(self):
+        """Per-kind block-Jacobi blocks P_t = (D - G_self M_t)^-1 (host FP64, then the device)."""
+        check(self.lib.aim_build_preconditioner(self._op))
+
+    def preconditioner(self) -> np.ndarray:
+        """The blocks P_t as (n_types, N, N) complex128."""
+        inf = self.info()
+        nt, N = inf["n_types"], inf["n_rwg"]
+        P = np.empty((nt, N, N), np.complex128)  # column-major per block: [t][col][row]
+        check(self.lib.aim_get_preconditioner(self._op, P.view(np.float64).ctypes.data_as(_lib._f64p)))
+        return np.ascontiguousarray(np.transpose(P, (0, 2, 1)))
+
+    def precond_apply(self, x, precision=AIM_FP64, out=None, stream=None):
+        R = self._check_vec(x, precision)
+        y = self._torch.empty_like(x) if out is None else out
+        check(self.lib.precond_apply(self._op, _dev_ptr(x), _dev_ptr(y), R, precision, _stream(self._torch, stream)))
+        return y
 
     def info(self) -> dict:
         inf = _lib.AimInfo()
@@ -166,12 +184,13 @@ class AimOperator:
         return b
 
     def gmres(self, b, x=None, *, restart=50, tol=1e-6, max_iters=1000, precision=AIM_FP64, check_every=1,
-              stream=None):
+              precond=0, stream=None):
         R = self._check_vec(b, AIM_FP64)
         x0_given = x is not None
         if x is None:
             x = self._torch.empty_like(b)
-        opts = GmresOpts(int(restart), int(max_iters), int(precision), int(x0_given), int(check_every), float(tol))
+        opts = GmresOpts(int(restart), int(max_iters), int(precision), int(x0_given), int(check_every), int(precond),
+                         float(tol))
         stats = (GmresStat * R)()
         code = check(self.lib.gmres_solve(self._op, _dev_ptr(b), _dev_ptr(x), R, ctypes.byref(opts), stats,
                                           _stream(self._torch, stream)))

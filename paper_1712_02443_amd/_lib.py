@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libaimm.so")
 AIM_OK, AIM_ENOCONV, AIM_EINVAL, AIM_ENOMEM, AIM_EDEVICE, AIM_ESTATE = 0, 1, -1, -2, -3, -4
 AIM_FP64, AIM_MIXED = 0, 1
 AIM_FULL, AIM_G_ONLY, AIM_FAR_ONLY = 0, 1, 2
+AIM_PRECOND_NONE, AIM_PRECOND_BLOCK_JACOBI = 0, 1
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f64p = ctypes.POINTER(ctypes.c_double)
@@ -45,7 +46,8 @@ class AimInfo(ctypes.Structure):
 
 class GmresOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("x0_given", ctypes.c_int32), ("check_every", ctypes.c_int32), ("tol", ctypes.c_double)]
+                ("x0_given", ctypes.c_int32), ("check_every", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("tol", ctypes.c_double)]
 
 
 class GmresStat(ctypes.Structure):
@@ -76,6 +78,10 @@ EXPORTS = {
                                           ctypes.c_void_p, ctypes.c_void_p]),
     "gmres_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                    ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresStat), ctypes.c_void_p]),
+    "aim_build_preconditioner": (ctypes.c_int, [ctypes.c_void_p]),
+    "aim_get_preconditioner": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
+    "precond_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_void_p]),
     "aim_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AimInfo)]),
     "aim_get_near": (ctypes.c_int, [ctypes.c_void_p, _i32p, _i32p, _i32p, _f64p, _i32p]),
     "aim_footprint_bytes": (ctypes.c_size_t, [ctypes.POINTER(AimSurface), ctypes.POINTER(AimArray),

@@ -10,6 +10,7 @@
 
 #include "../../include/aimm.h"
 #include "op.hpp"
+#include "precond.hpp"
 
 namespace aimm {
 
@@ -315,6 +316,25 @@ int matvec_impl(aim_op* op, const cplx<T>* x, cplx<T>* y, int R, int flags, hipS
 template int matvec_impl<double>(aim_op*, const cplx<double>*, cplx<double>*, int, int, hipStream_t, hipEvent_t*);
 template int matvec_impl<float>(aim_op*, const cplx<float>*, cplx<float>*, int, int, hipStream_t, hipEvent_t*);
 
+// y = blockdiag(P_t(m)) x, element-major in and out (grouped product, then the
+// transpose from its element-fastest output)
+template <typename T>
+int precond_impl(aim_op* op, const cplx<T>* x, cplx<T>* y, int R, hipStream_t s) {
+  cplx<T>* uT = static_cast<cplx<T>*>(op->u);
+  GemmArgs a = gemm_args(op, R);
+  a.Mb = op->gemm_bf16 ? op->Pb : nullptr;
+  const cplx<T>* P;
+  if constexpr (sizeof(T) == sizeof(double))
+    P = op->P64;
+  else
+    P = op->P32;
+  AIM_HIP(launch_macro<T>(P, x, uT, a, s));
+  AIM_HIP(launch_transpose<T>(uT, y, R, op->N, op->ne, s));
+  return AIM_OK;
+}
+template int precond_impl<double>(aim_op*, const cplx<double>*, cplx<double>*, int, hipStream_t);
+template int precond_impl<float>(aim_op*, const cplx<float>*, cplx<float>*, int, hipStream_t);
+
 template <typename T>
 static int time_kernels(aim_op* op, const cplx<T>* x, cplx<T>* y, int R, int reps, double* ms, hipStream_t s) {
   hipEvent_t ev[8];
@@ -551,59 +571,72 @@ static void split_bf16(float v, uint16_t out[3]) {
   out[2] = bf16_rne(r1 - bf16_to_float(out[1]));
 }
 
+// Device copies of one set of per-kind N x N blocks (host complex128 [n_types][N][N],
+// column-major): complex128 and complex64 with gemm_krows(N) columns per kind (zero
+// past N), and, for N % 8 == 0, the split-BF16 planes
+// [h, m, l of re; of im; of re + im][k / 8][row][k % 8] of the complex64 values.
+// Allocates on first use; throws std::bad_alloc or std::runtime_error.
+static void upload_blocks(aim_op* op, const cd* M, cplx<double>*& d64, cplx<float>*& d32, void*& db) {
+  const size_t N = size_t(op->N), kr = size_t(gemm_krows(op->N));
+  const size_t n = size_t(op->n_types) * kr * N;
+  if (!d64) {
+    d64 = op->mem.alloc<cplx<double>>(n);
+    d32 = op->mem.alloc<cplx<float>>(n);
+  }
+  std::vector<cplx<double>> m64(n, cplx<double>{0.0, 0.0});
+  std::vector<cplx<float>> m32(n, cplx<float>{0.0f, 0.0f});
+  for (size_t t = 0; t < size_t(op->n_types); ++t)
+    for (size_t e = 0; e < N * N; ++e) {
+      const size_t src = t * N * N + e, dst = t * kr * N + e;
+      m64[dst].re = M[src].real();
+      m64[dst].im = M[src].imag();
+      m32[dst].re = float(M[src].real());
+      m32[dst].im = float(M[src].imag());
+    }
+  if (hipMemcpy(d64, m64.data(), n * sizeof(cplx<double>), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(d32, m32.data(), n * sizeof(cplx<float>), hipMemcpyHostToDevice) != hipSuccess)
+    throw std::runtime_error("hipMemcpy of the block set failed");
+  if (op->N % 8 != 0) return;
+  const size_t KB = kr / 8, per = 9 * KB * N * 8;
+  std::vector<uint16_t> mb(size_t(op->n_types) * per, 0);
+  for (size_t t = 0; t < size_t(op->n_types); ++t)
+    for (size_t k = 0; k < kr; ++k)
+      for (size_t i = 0; i < N; ++i) {
+        const cplx<float> v = m32[t * kr * N + k * N + i];
+        const float comp[3] = {v.re, v.im, v.re + v.im};
+        for (int c = 0; c < 3; ++c) {
+          uint16_t part3[3];
+          split_bf16(comp[c], part3);
+          for (int q = 0; q < 3; ++q) mb[t * per + ((size_t(3 * c + q) * KB + k / 8) * N + i) * 8 + k % 8] = part3[q];
+        }
+      }
+  if (!db) db = op->mem.alloc<uint16_t>(mb.size());
+  if (hipMemcpy(db, mb.data(), mb.size() * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess)
+    throw std::runtime_error("hipMemcpy of the split-BF16 planes failed");
+}
+
 int aim_set_macromodels(aim_op* op, const double* M) {
   if (!op || !M) {
     set_error("op and M must not be NULL");
     return AIM_EINVAL;
   }
-  if (!op->device_ready) {
-    set_error("op was built without device data (aim_build_host)");
-    return AIM_ESTATE;
-  }
-  // device copy: per kind, gemm_krows(N) columns (column-major), zero past N
-  const size_t N = size_t(op->N), kr = size_t(gemm_krows(op->N));
-  const size_t n = size_t(op->n_types) * kr * N;
-  try {
-    if (!op->p64.M) {
-      op->p64.M = op->mem.alloc<cplx<double>>(n);
-      op->p32.M = op->mem.alloc<cplx<float>>(n);
+  const size_t nn = size_t(op->n_types) * op->N * op->N;
+  std::vector<cd> host(nn);
+  for (size_t e = 0; e < nn; ++e) host[e] = cd(M[2 * e], M[2 * e + 1]);
+  if (op->device_ready) {
+    try {
+      upload_blocks(op, host.data(), op->p64.M, op->p32.M, op->Mb);
+    } catch (const std::bad_alloc&) {
+      set_error("device allocation failed");
+      return AIM_ENOMEM;
+    } catch (const std::exception& e) {
+      set_error(e.what());
+      return AIM_EDEVICE;
     }
-    std::vector<cplx<double>> m64(n, cplx<double>{0.0, 0.0});
-    std::vector<cplx<float>> m32(n, cplx<float>{0.0f, 0.0f});
-    for (size_t t = 0; t < size_t(op->n_types); ++t)
-      for (size_t e = 0; e < N * N; ++e) {
-        const size_t src = t * N * N + e, dst = t * kr * N + e;
-        m64[dst].re = M[2 * src];
-        m64[dst].im = M[2 * src + 1];
-        m32[dst].re = float(M[2 * src]);
-        m32[dst].im = float(M[2 * src + 1]);
-      }
-    AIM_HIP(hipMemcpy(op->p64.M, m64.data(), n * sizeof(cplx<double>), hipMemcpyHostToDevice));
-    AIM_HIP(hipMemcpy(op->p32.M, m32.data(), n * sizeof(cplx<float>), hipMemcpyHostToDevice));
-    if (op->N % 8 == 0) {
-      // split-BF16 planes: per kind, [h, m, l of re; of im; of re + im][k / 8][row][k % 8]
-      const size_t KB = kr / 8, per = 9 * KB * N * 8;
-      std::vector<uint16_t> mb(size_t(op->n_types) * per, 0);
-      for (size_t t = 0; t < size_t(op->n_types); ++t)
-        for (size_t k = 0; k < kr; ++k)
-          for (size_t i = 0; i < N; ++i) {
-            const cplx<float> v = m32[t * kr * N + k * N + i];
-            const float comp[3] = {v.re, v.im, v.re + v.im};
-            for (int c = 0; c < 3; ++c) {
-              uint16_t part3[3];
-              split_bf16(comp[c], part3);
-              for (int q = 0; q < 3; ++q)
-                mb[t * per + ((size_t(3 * c + q) * KB + k / 8) * N + i) * 8 + k % 8] = part3[q];
-            }
-          }
-      if (!op->Mb) op->Mb = op->mem.alloc<uint16_t>(mb.size());
-      AIM_HIP(hipMemcpy(op->Mb, mb.data(), mb.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
-    }
-  } catch (const std::bad_alloc&) {
-    set_error("device allocation failed");
-    return AIM_ENOMEM;
   }
+  op->m_host.swap(host);
   op->m_set = true;
+  op->p_set = false;  // a preconditioner built from the previous blocks is stale
   return AIM_OK;
 }
 
@@ -622,9 +655,14 @@ int aim_set_dmatrix(aim_op* op, int64_t nnz, const int32_t* rows, const int32_t*
     set_error("D is already set");
     return AIM_ESTATE;
   }
+  op->d_rows.assign(rows, rows + nnz);
+  op->d_cols.assign(cols, cols + nnz);
+  op->d_vals.resize(size_t(nnz));
+  for (int64_t i = 0; i < nnz; ++i) op->d_vals[size_t(i)] = cd(vals[2 * i], vals[2 * i + 1]);
   if (!op->device_ready) {
-    set_error("op was built without device data (aim_build_host)");
-    return AIM_ESTATE;
+    op->d_nnz = nnz;
+    op->d_set = true;
+    return AIM_OK;
   }
   // padded row layout, slot-major: slot s of row n at s * N + n; entries keep their
   // input order within a row, padding slots point at column n with value 0
@@ -683,6 +721,67 @@ int macro_apply(aim_op* op, const void* x, void* u, int32_t nrhs, int32_t precis
     AIM_HIP(launch_transpose<float>(uT, static_cast<cplx<float>*>(u), nrhs, op->N, op->ne, s));
   }
   return AIM_OK;
+}
+
+int aim_build_preconditioner(aim_op* op) {
+  if (!op) {
+    set_error("op is NULL");
+    return AIM_EINVAL;
+  }
+  if (!op->m_set || !op->d_set) {
+    set_error("macromodels and D must be set before the preconditioner");
+    return AIM_ESTATE;
+  }
+  const size_t NN = size_t(op->N) * op->N;
+  try {
+    std::vector<cd> G, Pt, P(size_t(op->n_types) * NN);
+    self_block(op->st, op->arr, G);
+    for (int t = 0; t < op->n_types; ++t) {
+      block_inverse(G, op->m_host.data() + t * NN, op->d_rows.data(), op->d_cols.data(), op->d_vals.data(),
+                    int64_t(op->d_rows.size()), op->N, Pt);
+      std::copy(Pt.begin(), Pt.end(), P.begin() + t * NN);
+    }
+    if (op->device_ready) upload_blocks(op, P.data(), op->P64, op->P32, op->Pb);
+    op->p_host.swap(P);
+  } catch (const std::bad_alloc&) {
+    set_error("allocation failed");
+    return AIM_ENOMEM;
+  } catch (const std::runtime_error& e) {
+    set_error(e.what());
+    return op->device_ready && std::string(e.what()).find("hipMemcpy") != std::string::npos ? AIM_EDEVICE
+                                                                                               : AIM_EINVAL;
+  }
+  op->p_set = true;
+  return AIM_OK;
+}
+
+int aim_get_preconditioner(const aim_op* op, double* P) {
+  if (!op || !P) {
+    set_error("op and P must not be NULL");
+    return AIM_EINVAL;
+  }
+  if (!op->p_set) {
+    set_error("preconditioner not built (or stale after aim_set_macromodels)");
+    return AIM_ESTATE;
+  }
+  for (size_t e = 0; e < op->p_host.size(); ++e) {
+    P[2 * e] = op->p_host[e].real();
+    P[2 * e + 1] = op->p_host[e].imag();
+  }
+  return AIM_OK;
+}
+
+int precond_apply(aim_op* op, const void* x, void* y, int32_t nrhs, int32_t precision, void* stream) {
+  int c = check_common(op, x, y, nrhs, precision);
+  if (c) return c;
+  if (!op->p_set) {
+    set_error("preconditioner not built (or stale after aim_set_macromodels)");
+    return AIM_ESTATE;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (precision == AIM_FP64)
+    return precond_impl<double>(op, static_cast<const cplx<double>*>(x), static_cast<cplx<double>*>(y), nrhs, s);
+  return precond_impl<float>(op, static_cast<const cplx<float>*>(x), static_cast<cplx<float>*>(y), nrhs, s);
 }
 
 int aim_matvec(aim_op* op, const void* x, void* y, int32_t nrhs, int32_t precision, int32_t flags, void* stream) {

@@ -22,6 +22,8 @@ namespace aimm {
 
 template <typename T>
 int matvec_impl(aim_op* op, const cplx<T>* x, cplx<T>* y, int R, int flags, hipStream_t s, hipEvent_t* ev = nullptr);
+template <typename T>
+int precond_impl(aim_op* op, const cplx<T>* x, cplx<T>* y, int R, hipStream_t s);
 
 namespace {
 
@@ -639,6 +641,15 @@ __global__ void k_update_x(const cplx<Tb>* __restrict__ V, cplx<double>* __restr
   x[t] = acc;
 }
 
+__global__ void k_add(cplx<double>* __restrict__ x, const cplx<double>* __restrict__ d, int64_t n) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  cplx<double> v = x[t];
+  v.re += d[t].re;
+  v.im += d[t].im;
+  x[t] = v;
+}
+
 inline unsigned nblk(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
 
 // largest Krylov span the register-resident passes hold (two VGPRs per FP32 value)
@@ -711,6 +722,7 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
   KrylovWork& K = op->kw;
   const int64_t n = int64_t(op->ne) * op->N;
   const int m = o.restart;
+  const bool pre = o.precond == AIM_PRECOND_BLOCK_JACOBI;
   const int nch = int((n + kChunk - 1) / kChunk);
   const int nchs = int((n + kBS - 1) / kBS);  // chunks of the register-resident passes
   const dim3 gch(nch, R), bs(kBS), b64(64);
@@ -779,6 +791,12 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
       cplx<Tb>* unext = V + int64_t(j + 1) * R * n;
       const int nv = j + 1;
       const cplx<float>* wlo = nullptr;
+      if (pre) {
+        // right preconditioning: the product acts on z = P v_j (the residual buffer is free in a cycle)
+        rc = precond_impl<Tb>(op, uj, reinterpret_cast<cplx<Tb>*>(K.r), R, s);
+        if (rc) return rc;
+        uj = reinterpret_cast<const cplx<Tb>*>(K.r);
+      }
       if (sizeof(Tb) == sizeof(double)) {
         rc = matvec_impl<double>(op, reinterpret_cast<const cplx<double>*>(uj), K.w, R, AIM_FULL, s);
         if (rc) return rc;
@@ -824,7 +842,16 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
     }
     GM_LAUNCH(k_lsq, dim3(R), b64, sizeof(cplx<double>) * (size_t(m) * (m + 1) + m + 1), s, K.H, K.g, K.h2,
               K.active, m, R, j_end);
-    GM_LAUNCH(k_update_x<Tb>, dim3(nblk(n * R, 256)), dim3(256), 0, s, V, x, K.h2, K.ib, n, j_end, R, m);
+    if (pre) {
+      // x += P (V y), P applied in FP64
+      GM_HIP(hipMemsetAsync(K.w, 0, sizeof(cplx<double>) * n * R, s));
+      GM_LAUNCH(k_update_x<Tb>, dim3(nblk(n * R, 256)), dim3(256), 0, s, V, K.w, K.h2, K.ib, n, j_end, R, m);
+      rc = precond_impl<double>(op, K.w, K.r, R, s);
+      if (rc) return rc;
+      GM_LAUNCH(k_add, dim3(nblk(n * R, 256)), dim3(256), 0, s, x, K.r, n * R);
+    } else {
+      GM_LAUNCH(k_update_x<Tb>, dim3(nblk(n * R, 256)), dim3(256), 0, s, V, x, K.h2, K.ib, n, j_end, R, m);
+    }
     GM_HIP(hipMemcpyAsync(jused.data(), K.active, sizeof(int) * R, hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
     for (int r = 0; r < R; ++r) {
@@ -925,6 +952,14 @@ extern "C" int gmres_solve(aim_op* op, const void* b, void* x, int32_t nrhs, con
   if (b == x) {
     set_error("gmres: b and x must not alias");
     return AIM_EINVAL;
+  }
+  if (opts->precond != AIM_PRECOND_NONE && opts->precond != AIM_PRECOND_BLOCK_JACOBI) {
+    set_error("gmres: unknown preconditioner");
+    return AIM_EINVAL;
+  }
+  if (opts->precond == AIM_PRECOND_BLOCK_JACOBI && !op->p_set) {
+    set_error("gmres: block-Jacobi preconditioner not built (aim_build_preconditioner)");
+    return AIM_ESTATE;
   }
   if (!op->device_ready || !op->m_set || !op->d_set) {
     set_error("gmres: device data, macromodels and D must be set");

@@ -115,6 +115,16 @@ struct aim_op {
   int *nbr = nullptr, *d_colT = nullptr, *rev_x = nullptr, *rev_y = nullptr, *col_list = nullptr;
   aimm::PrecData<double> p64;
   aimm::PrecData<float> p32;
+  // host copies of the operator data, for the preconditioner's diagonal blocks
+  std::vector<aimm::cd> m_host;                 // [n_types][N][N] column-major
+  std::vector<int32_t> d_rows, d_cols;
+  std::vector<aimm::cd> d_vals;
+  // block-Jacobi preconditioner P_t = (D - G_self M_t)^-1, same device layouts as M
+  bool p_set = false;
+  std::vector<aimm::cd> p_host;                 // [n_types][N][N] column-major
+  aimm::cplx<double>* P64 = nullptr;
+  aimm::cplx<float>* P32 = nullptr;
+  void* Pb = nullptr;                           // split-BF16 planes of P (as Mb)
   void* u = nullptr;      // [R][N][n_elem] macromodel output, element-fastest (sized for complex128)
   void* nf = nullptr;     // [R][n_elem][N] near-field product (sized for complex128)
   void* grid = nullptr;   // Q / Phi (sized for complex128)

@@ -108,8 +108,10 @@ def test_device_calls_on_host_op_report_state(lib):
     code = lib.aim_matvec(op._op, buf, ctypes.c_void_p(2), 1, 0, 0, None)
     assert code == _lib.AIM_ESTATE
     assert b"aim_build_host" in lib.aim_last_error()
+    # operator data is accepted (kept on the host for the preconditioner); products are not
     M = np.zeros(2 * 288 * 288)
-    assert lib.aim_set_macromodels(op._op, M.ctypes.data_as(_lib._f64p)) == _lib.AIM_ESTATE
+    assert lib.aim_set_macromodels(op._op, M.ctypes.data_as(_lib._f64p)) == _lib.AIM_OK
+    assert lib.macro_apply(op._op, buf, ctypes.c_void_p(2), 1, 0, None) == _lib.AIM_ESTATE
     assert lib.aim_matvec(None, buf, buf, 1, 0, 0, None) == _lib.AIM_EINVAL
     op.close()
 
