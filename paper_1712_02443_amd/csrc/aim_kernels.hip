@@ -40,6 +40,41 @@ __device__ __forceinline__ void batched_copy(int n, Load f, Store g) {
 // gathers every basis of itself and of the neighbours whose stencil box covers g.
 
 // Node (lx, ly, lz) of element (ix, iy), its owner: sum over the covering cells.
+// Wp holds the four weights (psi = x, y, z, phi) of every gather entry in the order of
+// the gather table and node_n the entry's offset n * ne, so an entry costs two
+// wave-uniform loads and one coalesced load of u, with no dependent index load; eight
+// entries' loads are issued before their arithmetic.  A covering cell of a neighbour
+// outside the lattice reads the lane's own element instead and its sum is scaled by
+// zero (u is finite).
+template <typename T>
+__device__ __forceinline__ void project_cell(const cplx<T>* __restrict__ us, const ProjArgs& a,
+                                             const T* __restrict__ Wp, int e, int e1, cplx<T> (&acc)[4]) {
+  for (; e + 8 <= e1; e += 8) {
+    cplx<T> v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = us[a.node_n[e + u]];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) cfmas(acc[p], Wp[int64_t(e + u) * 4 + p], v[u]);
+  }
+  if (e + 4 <= e1) {
+    cplx<T> v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = us[a.node_n[e + u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) cfmas(acc[p], Wp[int64_t(e + u) * 4 + p], v[u]);
+    e += 4;
+  }
+  for (; e < e1; ++e) {
+    const cplx<T> v = us[a.node_n[e]];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) cfmas(acc[p], Wp[int64_t(e) * 4 + p], v);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void project_node(const cplx<T>* __restrict__ ur, cplx<T>* __restrict__ Qr,
                                              const ProjArgs& a, const T* __restrict__ Wp, int ix, int iy, int lx,
@@ -47,7 +82,6 @@ __device__ __forceinline__ void project_node(const cplx<T>* __restrict__ ur, cpl
   const int gx = ix * a.pitch + lx, gy = iy * a.pitch + ly;
   if (gx >= a.nx || gy >= a.ny) return;  // home cell of the last column / row past the grid
   const int m = iy * a.px + ix;
-  const int64_t NQ = int64_t(a.N) * a.q3;
   cplx<T> acc[4];
 #pragma unroll
   for (int p = 0; p < 4; ++p) acc[p] = cmk<T>(0, 0);
@@ -55,29 +89,17 @@ __device__ __forceinline__ void project_node(const cplx<T>* __restrict__ ur, cpl
     for (int dx = 0; lx + a.pitch * dx < a.ex; ++dx) {
       const int node = ((lx + a.pitch * dx) * a.ey + (ly + a.pitch * dy)) * a.ez + lz;
       const int e0 = a.node_ptr[node], e1 = a.node_ptr[node + 1];
-      const bool ok = ix - dx >= 0 && iy - dy >= 0;
-      const int ms = m - dx - dy * a.px;
-      int e = e0;
-      for (; e + 4 <= e1; e += 4) {
-        int ent[4];
-        cplx<T> v[4];
+      if (dx == 0 && dy == 0) {
+        project_cell(ur + m, a, Wp, e0, e1, acc);
+      } else {
+        const bool ok = ix - dx >= 0 && iy - dy >= 0;
+        cplx<T> c[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          ent[u] = a.node_ent[e + u];
-          const int n = a.node_n[e + u];
-          v[u] = ok ? ur[int64_t(n) * a.ne + ms] : cmk<T>(0, 0);
-        }
+        for (int p = 0; p < 4; ++p) c[p] = cmk<T>(0, 0);
+        project_cell(ur + (ok ? m - dx - dy * a.px : m), a, Wp, e0, e1, c);
+        const T f = ok ? T(1) : T(0);
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int p = 0; p < 4; ++p) cfmas(acc[p], Wp[p * NQ + ent[u]], v[u]);
-      }
-      for (; e < e1; ++e) {
-        const int ent = a.node_ent[e];
-        const int n = a.node_n[e];
-        const cplx<T> v = ok ? ur[int64_t(n) * a.ne + ms] : cmk<T>(0, 0);
-#pragma unroll
-        for (int p = 0; p < 4; ++p) cfmas(acc[p], Wp[p * NQ + ent], v);
+        for (int p = 0; p < 4; ++p) cfmas(acc[p], f, c[p]);
       }
     }
   }

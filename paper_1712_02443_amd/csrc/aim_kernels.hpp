@@ -18,8 +18,7 @@ struct ProjArgs {
   int ex, ey, ez;
   int nx, ny, nz, q3;
   const int* node_ptr;
-  const int* node_ent;
-  const int* node_n;
+  const int* node_n;  // per gather entry: n * ne (offset of basis n in the element-fastest u)
   const void* zero;  // one zero complex value (read for absent neighbours)
 };
 

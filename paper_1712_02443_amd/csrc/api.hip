@@ -78,6 +78,27 @@ static T* upload(aim_op* op, const T* host, size_t n) {
   return d;
 }
 
+// bf16 round-to-nearest-even of a finite float, and v = h + m + l in bf16 terms (each
+// remainder is exact in FP32)
+static uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+static float bf16_to_float(uint16_t b) {
+  const uint32_t u = uint32_t(b) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+static void split_bf16(float v, uint16_t out[3]) {
+  out[0] = bf16_rne(v);
+  const float r1 = v - bf16_to_float(out[0]);
+  out[1] = bf16_rne(r1);
+  out[2] = bf16_rne(r1 - bf16_to_float(out[1]));
+}
+
 template <typename T>
 static void fill_prec(aim_op* op, PrecData<T>& P) {
   const Setup& st = op->st;
@@ -85,11 +106,10 @@ static void fill_prec(aim_op* op, PrecData<T>& P) {
   std::vector<T> Wp(st.W.size()), Wt(st.W.size());
   for (int p = 0; p < 4; ++p)
     for (int n = 0; n < N; ++n)
-      for (int s = 0; s < q3; ++s) {
-        const double w = st.W[(size_t(p) * N + n) * q3 + s];
-        Wp[(size_t(p) * N + n) * q3 + s] = T(w);
-        Wt[(size_t(p) * q3 + s) * N + n] = T(w);
-      }
+      for (int s = 0; s < q3; ++s) Wt[(size_t(p) * q3 + s) * N + n] = T(st.W[(size_t(p) * N + n) * q3 + s]);
+  // projection: the four weights of each gather entry, in gather-table order
+  for (size_t e = 0; e < st.node_ent.size(); ++e)
+    for (int p = 0; p < 4; ++p) Wp[e * 4 + p] = T(st.W[size_t(p) * N * q3 + st.node_ent[e]]);
   P.Wp = upload(op, Wp.data(), Wp.size());
   P.Wt = upload(op, Wt.data(), Wt.size());
   std::vector<cplx<T>> nv(st.near_val.size());
@@ -161,7 +181,6 @@ static ProjArgs proj_args(aim_op* op, int R) {
   a.nz = st.nz;
   a.q3 = st.q3;
   a.node_ptr = op->node_ptr;
-  a.node_ent = op->node_ent;
   a.node_n = op->node_n;
   a.zero = op->zero;
   return a;
@@ -433,8 +452,11 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
     // integer tables
     op->sloc = upload(op, st.sloc.data(), st.sloc.size());
     op->node_ptr = upload(op, st.node_ptr.data(), st.node_ptr.size());
-    op->node_ent = upload(op, st.node_ent.data(), st.node_ent.size());
-    op->node_n = upload(op, st.node_n.data(), st.node_n.size());
+    // projection gather entries as offsets n * n_elem into the element-fastest u
+    if (int64_t(st.N) * op->ne > INT32_MAX) throw std::invalid_argument("n_rwg * n_elem exceeds 2^31");
+    std::vector<int32_t> noff(st.node_n.size());
+    for (size_t e = 0; e < noff.size(); ++e) noff[e] = st.node_n[e] * op->ne;
+    op->node_n = upload(op, noff.data(), noff.size());
     op->near_ptr = upload(op, st.near_ptr.data(), st.near_ptr.size());
     op->near_col = upload(op, st.near_col.data(), st.near_col.size());
     op->rev_x = upload(op, rx.data(), rx.size());
@@ -550,26 +572,6 @@ int aim_build_host(const aim_surface* surface, const aim_array* array, aim_op** 
   return build_op(surface, array, out, false);
 }
 
-// bf16 round-to-nearest-even of a finite float, and v = h + m + l in bf16 terms (each
-// remainder is exact in FP32)
-static uint16_t bf16_rne(float f) {
-  uint32_t u;
-  std::memcpy(&u, &f, 4);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return uint16_t(u >> 16);
-}
-static float bf16_to_float(uint16_t b) {
-  const uint32_t u = uint32_t(b) << 16;
-  float f;
-  std::memcpy(&f, &u, 4);
-  return f;
-}
-static void split_bf16(float v, uint16_t out[3]) {
-  out[0] = bf16_rne(v);
-  const float r1 = v - bf16_to_float(out[0]);
-  out[1] = bf16_rne(r1);
-  out[2] = bf16_rne(r1 - bf16_to_float(out[1]));
-}
 
 // Device copies of one set of per-kind N x N blocks (host complex128 [n_types][N][N],
 // column-major): complex128 and complex64 with gemm_krows(N) columns per kind (zero

@@ -45,7 +45,7 @@ struct DeviceMem {
 // Per-precision copies of the real and complex operator data.
 template <typename T>
 struct PrecData {
-  T* Wp = nullptr;           // [4][N * q3] projection weights, entry = n * q3 + p
+  T* Wp = nullptr;           // [N * q3][4] projection weights per gather entry, in gather-table order
   T* Wt = nullptr;           // [4][q3][N] interpolation weights
   cplx<T>* near = nullptr;   // pre-corrected near field
   cplx<T>* grpA = nullptr;   // near field as dense row-group blocks
@@ -102,7 +102,7 @@ struct aim_op {
   int d_max = 0;  // slots per row of the padded D layout
   size_t lds_max = 65536;
   aimm::DeviceMem mem;
-  int *sloc = nullptr, *node_ptr = nullptr, *node_ent = nullptr, *node_n = nullptr, *near_ptr = nullptr,
+  int *sloc = nullptr, *node_ptr = nullptr, *node_n = nullptr, *near_ptr = nullptr,
       *near_col = nullptr;
   int* offsets_d = nullptr;
   int *grp_ptr = nullptr, *grp_col = nullptr, *grp_row = nullptr, *slot_of = nullptr;
