@@ -211,8 +211,11 @@ def main() -> int:
     # depend on it: each right-hand side stops at its own first converged column)
     solve_kw = dict(restart=args.restart, tol=args.tol, max_iters=5000, check_every=5)
 
+    last_x = {}
+
     def solve(prec):
         x, st, code = op.gmres(b, precision=prec, **solve_kw)
+        last_x[prec] = x
         return st[0], code
 
     for _ in range(args.warmup):
@@ -288,6 +291,22 @@ def main() -> int:
             bj["mixed_vs_fp64_solve_speedup"] = bj["fp64_solve_ms"] / bj["mixed_solve_ms"]
         out["block_jacobi"] = bj
         print(f"[bench] block-Jacobi: {bj}", file=sys.stderr, flush=True)
+
+    # far field of the mixed solution along two principal cuts (0.5 degree steps)
+    th = np.linspace(0.0, math.pi, 361)
+    rh = np.concatenate([np.stack([np.sin(th), np.zeros_like(th), np.cos(th)], 1),
+                         np.stack([np.zeros_like(th), np.sin(th), np.cos(th)], 1)])
+    xs = last_x[AIM_MIXED]
+    op.far_field(xs, rh)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        op.far_field(xs, rh)
+    torch.cuda.synchronize()
+    ff_s = (time.perf_counter() - t) / args.steps
+    out["far_field"] = {"directions": int(rh.shape[0]), "ms": ff_s * 1e3,
+                        "element_sum_gflop": 8.0 * rh.shape[0] * info["n_rwg"] * info["n_elem"] / 1e9}
+    print(f"[bench] far field: {out['far_field']}", file=sys.stderr, flush=True)
 
     # standalone products
     x64 = torch.from_numpy(wl.test_vectors(1)).to("cuda")

@@ -228,6 +228,20 @@ int aim_get_preconditioner(const aim_op* op, double* P);
  * must not alias.  The grouped product of macro_apply with the blocks P_t. */
 int precond_apply(aim_op* op, const void* x, void* y, int32_t nrhs, int32_t precision, void* stream);
 
+/* Far field of the solution's equivalent currents, for the radiation patterns and
+ * bistatic RCS of section VI: with J = M x (section III) and element m centred at c_m,
+ *   E(r^) = -(j k eta / 4 pi) (I - r^ r^) . sum_m exp(j k r^ . c_m)
+ *           sum_n J_{m,n} int Lambda_n(r) exp(j k r^ . r) dS,
+ * the far-zone field E r exp(j k r) for unit incident amplitude, in FP64 (the sum over
+ * elements runs as a complex GEMM on the FP64 matrix cores).  x: device complex128
+ * [nrhs][n_unknowns] (a solution of gmres_solve); rhat: host [ndir][3] unit vectors;
+ * E: device complex128 [nrhs][ndir][3]; rcs_db: device double [nrhs][ndir] receiving
+ * 10 log10(4 pi |E|^2) (RCS in dB relative to a square wavelength), or NULL.  Needs
+ * the macromodels (AIM_ESTATE otherwise).  Allocates a device workspace on first use
+ * and when ndir grows, and keeps it with the op. */
+int aim_far_field(aim_op* op, const void* x, int32_t nrhs, int32_t ndir, const double* rhat, void* E,
+                  void* rcs_db, void* stream);
+
 /* Sizes of the op (host only, no device work). */
 int aim_get_info(const aim_op* op, aim_info* info);
 

@@ -267,6 +267,8 @@ static GemmArgs gemm_args(aim_op* op, int R) {
   return a;
 }
 
+GemmArgs gemm_args_of(aim_op* op, int R) { return gemm_args(op, R); }
+
 template <typename T>
 PrecData<T>& prec_data(aim_op* op);
 template <>

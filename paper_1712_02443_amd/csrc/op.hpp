@@ -82,6 +82,8 @@ struct KrylovWork {
 };
 
 void release_krylov(aim_op* op);
+// grouped-product arguments of the op's macromodel layout for R right-hand sides
+GemmArgs gemm_args_of(aim_op* op, int R);
 
 }  // namespace aimm
 
@@ -129,5 +131,8 @@ struct aim_op {
   void* nf = nullptr;     // [R][n_elem][N] near-field product (sized for complex128)
   void* grid = nullptr;   // Q / Phi (sized for complex128)
   void* S = nullptr;      // spectrum pass buffer (sized for complex128)
+  double* ff_quad = nullptr;  // far-field quadrature table [N][14][6], built on first use
+  void* ff_ws = nullptr;      // far-field workspace (directions, phase tables, partials)
+  size_t ff_bytes = 0;
   aimm::KrylovWork kw;
 };

@@ -596,6 +596,30 @@ void build_setup(const SurfaceIn& s, const ArrayIn& a, Setup& out) {
   out.grp_A.resize(out.grp_col.size() * kNearGroup, cd(0.0));
 }
 
+void far_quadrature(const SurfaceIn& s, std::vector<double>& q) {
+  const Mesh M = make_mesh(s);
+  q.assign(size_t(s.n_rwg) * 14 * 6, 0.0);
+  for (int n = 0; n < s.n_rwg; ++n) {
+    const Rwg& R = M.rwg[n];
+    for (int side = 0; side < 2; ++side) {
+      const Tri& t = M.tri[side == 0 ? R.tp : R.tm];
+      const V3 p = side == 0 ? R.pp : R.pm;
+      const double f = (side == 0 ? 1.0 : -1.0) * R.len / (2.0 * t.area);
+      for (int k = 0; k < 7; ++k) {
+        const V3 r = t.pts[k];
+        const V3 c = (f * R7.w[k] * t.area) * (r - p);
+        double* o = &q[(size_t(n) * 14 + side * 7 + k) * 6];
+        o[0] = r.x;
+        o[1] = r.y;
+        o[2] = r.z;
+        o[3] = c.x;
+        o[4] = c.y;
+        o[5] = c.z;
+      }
+    }
+  }
+}
+
 void plane_wave_local(const SurfaceIn& s, double k, double theta, double phi, int pol,
                       std::vector<cd>& loc, double kinc[3]) {
   const Mesh M = make_mesh(s);

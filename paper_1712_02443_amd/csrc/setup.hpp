@@ -66,6 +66,11 @@ void build_setup(const SurfaceIn& s, const ArrayIn& a, Setup& out);
 void plane_wave_local(const SurfaceIn& s, double k, double theta, double phi, int pol,
                       std::vector<cd>& loc, double kinc[3]);
 
+// Quadrature of the radiation integral F_n(r^) = int Lambda_n(r) exp(j k r^ . r) dS
+// (element-local r): per RWG n, 14 points (7 per triangle, T+ then T-) as
+// (x, y, z, c_x, c_y, c_z) with c = weight * area * Lambda_n(point).
+void far_quadrature(const SurfaceIn& s, std::vector<double>& q);
+
 // Smallest length >= n whose prime factors are 2, 3 and 5 only.
 int smooth_length(int n);
 // Radix factorisation (4, 2, 3, 5 preferred in that order); empty if not 5-smooth.

@@ -407,3 +407,23 @@ def test_gmres_matches_dense_solve(op0):
     assert info["converged"]
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-9
     assert info["restarts"] >= 2
+
+
+def test_radiated_field_reciprocity_with_plane_wave_rhs(op0):
+    """Reciprocity: the far field of currents J along rhat, polarisation e (e . rhat = 0),
+    equals (j k eta / 4 pi) sum_a J_a V_a for the plane wave arriving from rhat with
+    polarisation e (V of eq. V1), for two independently written integrals."""
+    from oracle.excitation import incidence, radiated_field
+    wl = op0.wl
+    rng = np.random.default_rng(5)
+    J = rng.standard_normal(wl.n_unknowns) + 1j * rng.standard_normal(wl.n_unknowns)
+    centers = wl.elem_center()
+    for th, ph in ((0.3, 1.1), (1.2, -2.0), (0.0, 0.0), (2.5, 0.4)):
+        rhat = np.array([[np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)]])
+        E = radiated_field(op0.geo, centers, J, rhat, wl.k, wl.eta)[0]
+        for pol in (0, 1):
+            _, e = incidence(th, ph, pol)
+            V = plane_wave_rhs(op0.geo, centers, th, ph, pol, wl.k)
+            ref = 1j * wl.k * wl.eta / (4 * np.pi) * np.sum(J * V)
+            assert abs(np.dot(e, E) - ref) <= 1e-12 * abs(ref)
+        assert abs(np.dot(rhat[0], E)) <= 1e-12 * np.linalg.norm(E)
