@@ -319,15 +319,25 @@ int matvec_impl(aim_op* op, const cplx<T>* x, cplx<T>* y, int R, int flags, hipS
   else
     AIM_HIP(launch_transpose<T>(x, uT, R, op->ne, op->N, s));
   if (ev) AIM_HIP(hipEventRecord(ev[1], s));
+  // the near field depends on u only: it runs on the op's second stream, concurrently
+  // with the projection and the FFT passes (in order on one stream when timing kernels)
+  NearArgs na = near_args(op, R);
+  if (op->near_mfma) na.grp_A = P.grpA;
+  const bool fork = !ev && op->s_aux && flags != AIM_FAR_ONLY;
+  if (fork) {
+    AIM_HIP(hipEventRecord(op->ev_fork, s));
+    AIM_HIP(hipStreamWaitEvent(op->s_aux, op->ev_fork, 0));
+    AIM_HIP(launch_near<T>(uT, nf, na, P.near, op->s_aux));
+    AIM_HIP(hipEventRecord(op->ev_join, op->s_aux));
+  }
   AIM_HIP(launch_project<T>(uT, grid, proj_args(op, R), P.Wp, s));
   if (ev) AIM_HIP(hipEventRecord(ev[2], s));
   AIM_HIP(launch_convolve<T>(grid, grid, S, conv_args(op, P, R), s, ev ? ev + 3 : nullptr));
   if (ev) AIM_HIP(hipEventRecord(ev[5], s));
-  if (flags != AIM_FAR_ONLY) {
-    NearArgs na = near_args(op, R);
-    if (op->near_mfma) na.grp_A = P.grpA;
+  if (fork)
+    AIM_HIP(hipStreamWaitEvent(s, op->ev_join, 0));
+  else if (flags != AIM_FAR_ONLY)
     AIM_HIP(launch_near<T>(uT, nf, na, P.near, s));
-  }
   if (ev) AIM_HIP(hipEventRecord(ev[6], s));
   AIM_HIP(launch_interp<T>(flags, grid, nf, x, y, interp_args<T>(op, R), P.Wt, P.dval, s));
   if (ev) AIM_HIP(hipEventRecord(ev[7], s));
@@ -447,6 +457,17 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
       return AIM_OK;
     }
     op->device_ready = true;
+    // a default-priority stream for the near field, joined back by events
+    if (hipStreamCreateWithFlags(&op->s_aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming) != hipSuccess)
+      throw std::runtime_error("stream or event creation failed");
+    if (const char* env = std::getenv("AIMM_SERIAL")) {
+      if (std::atoi(env) != 0) {
+        (void)hipStreamDestroy(op->s_aux);
+        op->s_aux = nullptr;
+      }
+    }
     if (hipGetDevice(&op->device) != hipSuccess) throw std::runtime_error("no HIP device");
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, op->device) != hipSuccess) throw std::runtime_error("device query failed");
@@ -995,6 +1016,9 @@ void aim_destroy(aim_op* op) {
   if (op->device_ready) {
     (void)hipDeviceSynchronize();
     aimm::release_krylov(op);
+    if (op->s_aux) (void)hipStreamDestroy(op->s_aux);
+    if (op->ev_fork) (void)hipEventDestroy(op->ev_fork);
+    if (op->ev_join) (void)hipEventDestroy(op->ev_join);
   }
   delete op;
 }

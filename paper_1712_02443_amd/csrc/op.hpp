@@ -131,6 +131,9 @@ struct aim_op {
   void* nf = nullptr;     // [R][n_elem][N] near-field product (sized for complex128)
   void* grid = nullptr;   // Q / Phi (sized for complex128)
   void* S = nullptr;      // spectrum pass buffer (sized for complex128)
+  // the near field runs on a second stream, beside step (i) and the FFT passes
+  hipStream_t s_aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double* ff_quad = nullptr;  // far-field quadrature table [N][14][6], built on first use
   void* ff_ws = nullptr;      // far-field workspace (directions, phase tables, partials)
   size_t ff_bytes = 0;
