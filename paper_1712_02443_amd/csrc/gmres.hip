@@ -730,20 +730,28 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
   GM_LAUNCH(k_residual, gch, bs, 0, s, b, (const cplx<double>*)nullptr, (cplx<double>*)nullptr, K.part, n);
   GM_LAUNCH(k_finish_norm, dim3(R), bs, 0, s, K.part, K.scal + 3, nch, R, 4);
   if (!o.x0_given) GM_HIP(hipMemsetAsync(x, 0, sizeof(cplx<double>) * n * R, s));
-  std::vector<double> bnorm(R), relres(R, 1.0), hs(4 * R);
-  std::vector<int> active(R, 1), iters(R, 0), restarts(R, 0), matvecs(R, 0), jused(R), jinit(R);
-  GM_HIP(hipMemcpyAsync(hs.data(), K.scal, sizeof(double) * 4 * R, hipMemcpyDeviceToHost, s));
+  // host sides of the small transfers live in pinned memory (K.h_*); the host writes a
+  // staging array only after a stream synchronisation that follows its last transfer
+  std::vector<double> bnorm(R), relres(R, 1.0);
+  std::vector<int> active(R, 1), iters(R, 0), restarts(R, 0), matvecs(R, 0);
+  double* hs = K.h_scal;
+  int *jused = K.h_jused, *jinit = K.h_jinit;
+  cplx<double>*g0 = K.h_g0, *gh = K.h_gh;
+  double* ib0 = K.h_ib0;
+  const size_t gl = size_t(R) * (m + 1);
+  GM_HIP(hipMemcpyAsync(hs, K.scal, sizeof(double) * 4 * R, hipMemcpyDeviceToHost, s));
   GM_HIP(hipStreamSynchronize(s));
   for (int r = 0; r < R; ++r) bnorm[r] = hs[4 * r + 3];
-  std::vector<cplx<double>> g0(size_t(R) * (m + 1));
-  std::vector<double> ib0(size_t(R) * (m + 1), 0.0);  // s_0 = 1: v_0 is stored normalised
-  for (int r = 0; r < R; ++r) ib0[size_t(r) * (m + 1)] = 1.0;
+  for (size_t i = 0; i < gl; ++i) {
+    g0[i] = cplx<double>{0.0, 0.0};
+    ib0[i] = 0.0;
+  }
+  for (int r = 0; r < R; ++r) ib0[size_t(r) * (m + 1)] = 1.0;  // s_0 = 1: v_0 is stored normalised
   const int check = std::max(1, o.check_every);
   // Host checks of the stop flags: a check costs a round trip, a late one costs the
   // iterations run past convergence.  Each check extrapolates every running residual
   // estimate geometrically from the previous check and places the next check where
   // the slowest is predicted to pass its threshold (at most check_every ahead).
-  std::vector<cplx<double>> gh(size_t(R) * (m + 1));
   std::vector<double> est_prev(R);
   std::vector<int> j_prev(R);
   bool x_zero = !o.x0_given;
@@ -753,7 +761,7 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
     if (rc) return rc;
     GM_LAUNCH(k_residual, gch, bs, 0, s, b, x_zero ? (const cplx<double>*)nullptr : K.w, K.r, K.part, n);
     GM_LAUNCH(k_finish_norm, dim3(R), bs, 0, s, K.part, K.scal, nch, R, 4);
-    GM_HIP(hipMemcpyAsync(hs.data(), K.scal, sizeof(double) * 4 * R, hipMemcpyDeviceToHost, s));
+    GM_HIP(hipMemcpyAsync(hs, K.scal, sizeof(double) * 4 * R, hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
     bool any = false;
     int budget_max = 0;
@@ -775,10 +783,10 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
       jinit[r] = active[r] ? 0 : -1;
       g0[size_t(r) * (m + 1)] = cplx<double>{active[r] ? hs[4 * r] : 0.0, 0.0};
     }
-    GM_HIP(hipMemcpyAsync(K.scal, hs.data(), sizeof(double) * 4 * R, hipMemcpyHostToDevice, s));
-    GM_HIP(hipMemcpyAsync(K.active, jinit.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
-    GM_HIP(hipMemcpyAsync(K.g, g0.data(), sizeof(cplx<double>) * g0.size(), hipMemcpyHostToDevice, s));
-    GM_HIP(hipMemcpyAsync(K.ib, ib0.data(), sizeof(double) * ib0.size(), hipMemcpyHostToDevice, s));
+    GM_HIP(hipMemcpyAsync(K.scal, hs, sizeof(double) * 4 * R, hipMemcpyHostToDevice, s));
+    GM_HIP(hipMemcpyAsync(K.active, jinit, sizeof(int) * R, hipMemcpyHostToDevice, s));
+    GM_HIP(hipMemcpyAsync(K.g, g0, sizeof(cplx<double>) * gl, hipMemcpyHostToDevice, s));
+    GM_HIP(hipMemcpyAsync(K.ib, ib0, sizeof(double) * gl, hipMemcpyHostToDevice, s));
     GM_LAUNCH(k_scale<Tb>, dim3(nblk(n * R, 256)), dim3(256), 0, s, K.r, V, K.scal, 4, n, R);
     x_zero = false;
     for (int r = 0; r < R; ++r) {
@@ -817,8 +825,8 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
                 j, R);
       j_end = j + 1;
       if (j_end >= next_check || j_end == budget_max) {
-        GM_HIP(hipMemcpyAsync(jused.data(), K.active, sizeof(int) * R, hipMemcpyDeviceToHost, s));
-        GM_HIP(hipMemcpyAsync(gh.data(), K.g, sizeof(cplx<double>) * gh.size(), hipMemcpyDeviceToHost, s));
+        GM_HIP(hipMemcpyAsync(jused, K.active, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+        GM_HIP(hipMemcpyAsync(gh, K.g, sizeof(cplx<double>) * gl, hipMemcpyDeviceToHost, s));
         GM_HIP(hipStreamSynchronize(s));
         bool all = true;
         int ahead = 1;
@@ -852,7 +860,7 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
     } else {
       GM_LAUNCH(k_update_x<Tb>, dim3(nblk(n * R, 256)), dim3(256), 0, s, V, x, K.h2, K.ib, n, j_end, R, m);
     }
-    GM_HIP(hipMemcpyAsync(jused.data(), K.active, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    GM_HIP(hipMemcpyAsync(jused, K.active, sizeof(int) * R, hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
     for (int r = 0; r < R; ++r) {
       if (!active[r]) continue;
@@ -879,6 +887,7 @@ void free_krylov(KrylovWork& K) {
                 K.hcol, K.h2, K.part, K.scal, K.active, K.S, K.ib, K.pq, K.cr};
   for (void* p : ps)
     if (p) (void)hipFree(p);
+  if (K.hpin) (void)hipHostFree(K.hpin);
   K = KrylovWork{};
 }
 
@@ -916,6 +925,27 @@ int ensure_krylov(aim_op* op, int R, int m, int prec) {
   al(reinterpret_cast<void**>(&K.part), sizeof(double) * K.part_len);
   al(reinterpret_cast<void**>(&K.scal), sizeof(double) * 4 * R);
   al(reinterpret_cast<void**>(&K.active), sizeof(int) * R);
+  {
+    // pinned staging: [R][4] doubles, 2 x [R] ints, 2 x [R][m+1] complex, [R][m+1] doubles
+    const size_t gl = size_t(R) * (m + 1);
+    auto up8 = [](size_t b) { return (b + 15) / 16 * 16; };
+    const size_t o1 = up8(sizeof(double) * 4 * R), o2 = o1 + up8(sizeof(int) * R), o3 = o2 + up8(sizeof(int) * R),
+                 o4 = o3 + sizeof(cplx<double>) * gl, o5 = o4 + sizeof(cplx<double>) * gl,
+                 end = o5 + sizeof(double) * gl;
+    if (ok && hipHostMalloc(&K.hpin, end, hipHostMallocDefault) != hipSuccess) {
+      K.hpin = nullptr;
+      ok = false;
+    }
+    if (ok) {
+      unsigned char* h = static_cast<unsigned char*>(K.hpin);
+      K.h_scal = reinterpret_cast<double*>(h);
+      K.h_jinit = reinterpret_cast<int*>(h + o1);
+      K.h_jused = reinterpret_cast<int*>(h + o2);
+      K.h_g0 = reinterpret_cast<cplx<double>*>(h + o3);
+      K.h_gh = reinterpret_cast<cplx<double>*>(h + o4);
+      K.h_ib0 = reinterpret_cast<double*>(h + o5);
+    }
+  }
   if (!ok) {
     free_krylov(K);
     set_error("gmres: device allocation of the Krylov workspace failed");

@@ -79,6 +79,14 @@ struct KrylovWork {
   cplx<double>* pq = nullptr; // [R][2 (restart+1)] projections and new Gram column
   cplx<double>* cr = nullptr; // [R][restart+1] update coefficients of the stored u_i
   int* active = nullptr;      // [R] per-cycle stop column
+  // pinned host staging for the per-cycle and per-check transfers (asynchronous DMA)
+  void* hpin = nullptr;
+  double* h_scal = nullptr;        // [R][4]
+  int* h_jinit = nullptr;          // [R]
+  int* h_jused = nullptr;          // [R]
+  cplx<double>* h_g0 = nullptr;    // [R][restart+1]
+  cplx<double>* h_gh = nullptr;    // [R][restart+1]
+  double* h_ib0 = nullptr;         // [R][restart+1]
 };
 
 void release_krylov(aim_op* op);
@@ -106,14 +114,14 @@ struct aim_op {
   aimm::DeviceMem mem;
   int *sloc = nullptr, *node_ptr = nullptr, *node_n = nullptr, *near_ptr = nullptr,
       *near_col = nullptr;
-  int* offsets_d = nullptr;
+  int* offsets_d = nullptr;  // [n_off][2] lattice offsets of the near-field blocks
   int *grp_ptr = nullptr, *grp_col = nullptr, *grp_row = nullptr, *slot_of = nullptr;
   aimm::cplx<double>* zero = nullptr;  // one zero value (16 bytes; also read as complex64)
   bool near_mfma = true;
   bool fft4 = false;  // register-DFT FFT passes
   bool gemm_bf16 = false;  // mixed-path macromodel product on the bf16 matrix cores (split in three)
   void* Mb = nullptr;      // [n_types][9 planes][Krows / 8][N][8] bf16
-  int interp_tx = 0, interp_ty = 0;  // 0 = automatic  // [n_off][2] lattice offsets of the near-field blocks
+  int interp_tx = 0, interp_ty = 0;  // interpolation tile (0 = automatic)
   int *nbr = nullptr, *d_colT = nullptr, *rev_x = nullptr, *rev_y = nullptr, *col_list = nullptr;
   aimm::PrecData<double> p64;
   aimm::PrecData<float> p32;
