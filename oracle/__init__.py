@@ -16,7 +16,9 @@ What it computes, each function citing the passage of the paper it follows:
     with T A^-1 B given as the per-type block M_t (section III);
   * GMRES(m) on the final system (section V, eq. finalsystem), optionally right
     preconditioned with the per-kind block-Jacobi inverse of the diagonal blocks;
-  * the plane-wave excitation vector (section IV eq. V1).
+  * the plane-wave excitation vector (section IV eq. V1) and the radiated far field;
+  * the Mie series of a perfectly conducting sphere, an analytic reference for the
+    EFIE, excitation and far field together.
 
 Floating point is IEEE double throughout; numpy / scipy supply matmul and FFT
 steps.  Readings of points the paper leaves open are listed where they are used.

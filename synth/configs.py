@@ -82,7 +82,7 @@ class Workload:
 
     @property
     def n_rwg(self) -> int:
-        return 18 * self.box_n * self.box_n
+        return self.surface.n_rwg
 
     @property
     def n_unknowns(self) -> int:

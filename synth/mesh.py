@@ -131,3 +131,39 @@ def vertex_triangles(mesh: SurfaceMesh) -> list[list[int]]:
         for v in row:
             out[int(v)].append(t)
     return out
+
+
+def icosphere(radius: float, level: int) -> SurfaceMesh:
+    """Closed triangulated sphere: an icosahedron whose faces are split in four `level`
+    times, vertices pushed onto the sphere (20 * 4**level triangles)."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    verts = [np.asarray(p, dtype=np.float64) / np.linalg.norm(p) for p in v]
+    faces = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+             (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5),
+             (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(level):
+        mid: dict[tuple[int, int], int] = {}
+
+        def midpoint(a: int, b: int) -> int:
+            key = (min(a, b), max(a, b))
+            if key not in mid:
+                p = verts[a] + verts[b]
+                verts.append(p / np.linalg.norm(p))
+                mid[key] = len(verts) - 1
+            return mid[key]
+
+        nf = []
+        for a, b, c in faces:
+            ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        faces = nf
+    vert = radius * np.asarray(verts)
+    tri = np.asarray(faces, dtype=np.int32)
+    # counter-clockwise seen from outside: the right-hand normal points away from the centre
+    p = vert[tri]
+    nrm = np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0])
+    flip = np.einsum("ij,ij->i", nrm, p.mean(1)) < 0
+    tri[flip] = tri[flip][:, [0, 2, 1]]
+    return SurfaceMesh(vert, tri, rwg_table(tri))
