@@ -159,6 +159,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solves")
     ap.add_argument("--no-precond", action="store_true", help="skip the block-Jacobi preconditioned solves")
+    ap.add_argument("--no-standard-mom", action="store_true",
+                    help="skip the standard AIM-MoM solves on the original Jerusalem-cross surfaces")
     ap.add_argument("--profile-products", type=int, default=0,
                     help="only run this many FP32 and FP64 products and a 512 MiB device copy "
                          "(the copy calibrates hardware byte counters), then exit")
@@ -177,8 +179,8 @@ def main() -> int:
     import numpy as np
     import torch
 
-    from paper_1712_02443_amd import AIM_FP64, AIM_MIXED, AIM_PRECOND_BLOCK_JACOBI, AimOperator
-    from synth import make_workload
+    from paper_1712_02443_amd import AIM_FP64, AIM_G_ONLY, AIM_MIXED, AIM_PRECOND_BLOCK_JACOBI, AimOperator
+    from synth import make_workload, standard_mom_workload
 
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
@@ -307,6 +309,45 @@ def main() -> int:
     out["far_field"] = {"directions": int(rh.shape[0]), "ms": ff_s * 1e3,
                         "element_sum_gflop": 8.0 * rh.shape[0] * info["n_rwg"] * info["n_elem"] / 1e9}
     print(f"[bench] far field: {out['far_field']}", file=sys.stderr, flush=True)
+
+    if not args.no_standard_mom:
+        # the same array solved as a standard AIM-MoM on each element's own PEC surface
+        # (1,196 RWG per cross instead of the 648 of its equivalent box): G J = V
+        ws = standard_mom_workload()
+        t = time.perf_counter()
+        ops = AimOperator.from_workload(ws)
+        torch.cuda.synchronize()
+        sm = {"workload": f"{ws.name}: 32x32 PEC Jerusalem crosses, {ws.n_rwg} RWG each", "unknowns": ws.n_unknowns,
+              "macromodel_unknowns": wl.n_unknowns, "build_s": time.perf_counter() - t}
+        bs = ops.plane_wave_rhs(ws.theta, ws.phi, ws.pol)
+        skw = dict(restart=args.restart, tol=args.tol, max_iters=5000, check_every=5, precision=AIM_MIXED,
+                   system=AIM_G_ONLY)
+        ops.gmres(bs, **skw)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, sts, cs = ops.gmres(bs, **skw)
+        torch.cuda.synchronize()
+        sm.update({"mixed_solve_ms": (time.perf_counter() - t) * 1e3, "iters": sts[0]["iters"],
+                   "converged": bool(sts[0]["converged"]), "true_relres": sts[0]["true_relres"]})
+        # block-Jacobi on the crosses: blocks G_self^-1 (built with M = -I, empty D)
+        t = time.perf_counter()
+        ops.set_macromodels(-np.eye(ws.n_rwg, dtype=np.complex128)[None])
+        ops.set_dmatrix(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.complex128))
+        ops.build_preconditioner()
+        torch.cuda.synchronize()
+        sm["block_jacobi_setup_s"] = time.perf_counter() - t
+        skw["precond"] = AIM_PRECOND_BLOCK_JACOBI
+        ops.gmres(bs, **skw)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, sts, cs = ops.gmres(bs, **skw)
+        torch.cuda.synchronize()
+        sm.update({"block_jacobi_mixed_solve_ms": (time.perf_counter() - t) * 1e3,
+                   "block_jacobi_iters": sts[0]["iters"], "block_jacobi_converged": bool(sts[0]["converged"])})
+        ops.close()
+        del ops
+        out["standard_mom"] = sm
+        print(f"[bench] standard MoM: {sm}", file=sys.stderr, flush=True)
 
     # standalone products
     x64 = torch.from_numpy(wl.test_vectors(1)).to("cuda")

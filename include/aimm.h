@@ -183,6 +183,11 @@ typedef struct {
                            (right preconditioning, A P z = b, x = P z, with the
                            blocks of aim_build_preconditioner; the residual that
                            tol and the stats refer to is still b - A x) */
+  int32_t system;       /* AIM_FULL: A = D - G M, the final system (eq. finalsystem);
+                           AIM_G_ONLY: A = G, the EFIE of the surfaces themselves
+                           (standard MoM on scatterer meshes: no macromodels or D
+                           needed; block-Jacobi then wants blocks built with
+                           M_t = -I and an empty D, which make them G_self^-1) */
   double tol;           /* relative residual target ||b - A x|| / ||b|| */
 } gmres_opts;
 
@@ -229,7 +234,8 @@ int aim_get_preconditioner(const aim_op* op, double* P);
 int precond_apply(aim_op* op, const void* x, void* y, int32_t nrhs, int32_t precision, void* stream);
 
 /* Far field of the solution's equivalent currents, for the radiation patterns and
- * bistatic RCS of section VI: with J = M x (section III) and element m centred at c_m,
+ * bistatic RCS of section VI: with J = M x (section III; J = x when system is
+ * AIM_G_ONLY, the surface currents of a standard MoM solve) and element m centred at c_m,
  *   E(r^) = -(j k eta / 4 pi) (I - r^ r^) . sum_m exp(j k r^ . c_m)
  *           sum_n J_{m,n} int Lambda_n(r) exp(j k r^ . r) dS,
  * the far-zone field E r exp(j k r) for unit incident amplitude, in FP64 (the sum over
@@ -237,10 +243,10 @@ int precond_apply(aim_op* op, const void* x, void* y, int32_t nrhs, int32_t prec
  * [nrhs][n_unknowns] (a solution of gmres_solve); rhat: host [ndir][3] unit vectors;
  * E: device complex128 [nrhs][ndir][3]; rcs_db: device double [nrhs][ndir] receiving
  * 10 log10(4 pi |E|^2) (RCS in dB relative to a square wavelength), or NULL.  Needs
- * the macromodels (AIM_ESTATE otherwise).  Allocates a device workspace on first use
+ * the macromodels for AIM_FULL (AIM_ESTATE otherwise).  Allocates a device workspace on first use
  * and when ndir grows, and keeps it with the op. */
 int aim_far_field(aim_op* op, const void* x, int32_t nrhs, int32_t ndir, const double* rhat, void* E,
-                  void* rcs_db, void* stream);
+                  void* rcs_db, int32_t system, void* stream);
 
 /* Sizes of the op (host only, no device work). */
 int aim_get_info(const aim_op* op, aim_info* info);

@@ -47,7 +47,7 @@ class AimInfo(ctypes.Structure):
 class GmresOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("x0_given", ctypes.c_int32), ("check_every", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("tol", ctypes.c_double)]
+                ("system", ctypes.c_int32), ("tol", ctypes.c_double)]
 
 
 class GmresStat(ctypes.Structure):
@@ -83,7 +83,7 @@ EXPORTS = {
     "precond_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                      ctypes.c_int32, ctypes.c_void_p]),
     "aim_far_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, _f64p,
-                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "aim_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AimInfo)]),
     "aim_get_near": (ctypes.c_int, [ctypes.c_void_p, _i32p, _i32p, _i32p, _f64p, _i32p]),
     "aim_footprint_bytes": (ctypes.c_size_t, [ctypes.POINTER(AimSurface), ctypes.POINTER(AimArray),

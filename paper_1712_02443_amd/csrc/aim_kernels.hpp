@@ -23,7 +23,7 @@ struct ProjArgs {
 };
 
 // FFT lengths L = L1 L2 with register-DFT (four-step) passes
-#define AIM_F4_LENGTHS(X) X(3, 9) X(5, 8) X(6, 9) X(8, 8) X(10, 20) X(20, 20) X(25, 32)
+#define AIM_F4_LENGTHS(X) X(3, 9) X(5, 8) X(6, 9) X(8, 8) X(10, 20) X(16, 24) X(20, 20) X(25, 32)
 bool fft4_supported(int L);
 
 struct ConvArgs {

@@ -187,7 +187,7 @@ using namespace aimm;
   } while (0)
 
 extern "C" int aim_far_field(aim_op* op, const void* x, int32_t nrhs, int32_t ndir, const double* rhat, void* E,
-                             void* rcs_db, void* stream) {
+                             void* rcs_db, int32_t system, void* stream) {
   if (!op || !x || !rhat || !E || ndir < 1) {
     set_error("far field: op, x, rhat and E must not be NULL and ndir >= 1");
     return AIM_EINVAL;
@@ -201,7 +201,11 @@ extern "C" int aim_far_field(aim_op* op, const void* x, int32_t nrhs, int32_t nd
       set_error("far field: directions must be finite");
       return AIM_EINVAL;
     }
-  if (!op->device_ready || !op->m_set) {
+  if (system != AIM_FULL && system != AIM_G_ONLY) {
+    set_error("far field: system must be AIM_FULL or AIM_G_ONLY");
+    return AIM_EINVAL;
+  }
+  if (!op->device_ready || (system == AIM_FULL && !op->m_set)) {
     set_error("far field: device data and macromodels must be set");
     return AIM_ESTATE;
   }
@@ -245,10 +249,14 @@ extern "C" int aim_far_field(aim_op* op, const void* x, int32_t nrhs, int32_t nd
   cplx<double>* Y = X + size_t(ndir) * px;
   cplx<double>* part = Y + size_t(ndir) * py;
   FF_HIP(hipMemcpyAsync(rd, rhat, size_t(ndir) * 3 * sizeof(double), hipMemcpyHostToDevice, s));
-  // equivalent currents J = M x, element-fastest
+  // currents J = M x (or x itself), element-fastest
   cplx<double>* uT = static_cast<cplx<double>*>(op->u);
-  GemmArgs ga = gemm_args_of(op, nrhs);
-  FF_HIP(launch_macro<double>(op->p64.M, static_cast<const cplx<double>*>(x), uT, ga, s));
+  if (system == AIM_FULL) {
+    GemmArgs ga = gemm_args_of(op, nrhs);
+    FF_HIP(launch_macro<double>(op->p64.M, static_cast<const cplx<double>*>(x), uT, ga, s));
+  } else {
+    FF_HIP(launch_transpose<double>(static_cast<const cplx<double>*>(x), uT, nrhs, ne, N, s));
+  }
   const double kp = op->arr.k * op->arr.pitch * op->arr.h;
   const int nt = ndir * (px + py);
   hipLaunchKernelGGL(k_ff_tables, dim3((nt + 255) / 256), dim3(256), 0, s, rd, X, Y, ndir, px, py, kp);

@@ -723,6 +723,7 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
   const int64_t n = int64_t(op->ne) * op->N;
   const int m = o.restart;
   const bool pre = o.precond == AIM_PRECOND_BLOCK_JACOBI;
+  const int sys = o.system;  // AIM_FULL: the final system; AIM_G_ONLY: G x = b
   const int nch = int((n + kChunk - 1) / kChunk);
   const int nchs = int((n + kBS - 1) / kBS);  // chunks of the register-resident passes
   const dim3 gch(nch, R), bs(kBS), b64(64);
@@ -757,7 +758,7 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
   bool x_zero = !o.x0_given;
   for (;;) {
     // FP64 true residual r = b - A x (no product while x is still the zero start)
-    int rc = x_zero ? AIM_OK : matvec_impl<double>(op, x, K.w, R, AIM_FULL, s);
+    int rc = x_zero ? AIM_OK : matvec_impl<double>(op, x, K.w, R, sys, s);
     if (rc) return rc;
     GM_LAUNCH(k_residual, gch, bs, 0, s, b, x_zero ? (const cplx<double>*)nullptr : K.w, K.r, K.part, n);
     GM_LAUNCH(k_finish_norm, dim3(R), bs, 0, s, K.part, K.scal, nch, R, 4);
@@ -806,11 +807,11 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
         uj = reinterpret_cast<const cplx<Tb>*>(K.r);
       }
       if (sizeof(Tb) == sizeof(double)) {
-        rc = matvec_impl<double>(op, reinterpret_cast<const cplx<double>*>(uj), K.w, R, AIM_FULL, s);
+        rc = matvec_impl<double>(op, reinterpret_cast<const cplx<double>*>(uj), K.w, R, sys, s);
         if (rc) return rc;
       } else {
         rc = matvec_impl<float>(op, reinterpret_cast<const cplx<float>*>(uj), static_cast<cplx<float>*>(K.ylow), R,
-                                AIM_FULL, s);
+                                sys, s);
         if (rc) return rc;
         wlo = static_cast<const cplx<float>*>(K.ylow);
       }
@@ -991,7 +992,11 @@ extern "C" int gmres_solve(aim_op* op, const void* b, void* x, int32_t nrhs, con
     set_error("gmres: block-Jacobi preconditioner not built (aim_build_preconditioner)");
     return AIM_ESTATE;
   }
-  if (!op->device_ready || !op->m_set || !op->d_set) {
+  if (opts->system != AIM_FULL && opts->system != AIM_G_ONLY) {
+    set_error("gmres: system must be AIM_FULL or AIM_G_ONLY");
+    return AIM_EINVAL;
+  }
+  if (!op->device_ready || (opts->system == AIM_FULL && (!op->m_set || !op->d_set))) {
     set_error("gmres: device data, macromodels and D must be set");
     return AIM_ESTATE;
   }

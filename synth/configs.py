@@ -29,7 +29,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .mesh import SurfaceMesh, cube_surface
+from .mesh import SurfaceMesh, cube_surface, jerusalem_cross
 
 ETA0 = 376.730313668
 K0 = 2.0 * math.pi
@@ -200,6 +200,19 @@ def make_workload(index: int, seed: int = 0, px: int | None = None, py: int | No
         return Workload("jc-64x64-8rhs", P, Q, 0.55, 6, 2, types, th, np.zeros(n), pol,
                         restart=80, seed=seed)
     raise ValueError(f"no workload {index} (workload 3 is the request trace, see serving_trace)")
+
+
+def standard_mom_workload(px: int = 32, py: int | None = None, cell: float = 0.01, seed: int = 0) -> Workload:
+    """The 32 x 32 Jerusalem-cross array of workload 1 with each element's own PEC
+    surface meshed (arms 0.4, width 0.04, caps 0.2 x 0.02 wavelength on `cell`-sized
+    squares: 1,196 RWG at 0.01) instead of its equivalent box: the system a standard
+    AIM-MoM solves, G J = V, for the unknown-count and iteration comparison with the
+    macromodel system.  Same lattice, AIM grid, near radius and incidence as workload 1."""
+    P = px
+    Q = P if py is None else py
+    return Workload("jc-32x32-standard-mom", P, Q, 0.0, 0, 1, np.zeros(P * Q, dtype=np.int32),
+                    np.full(1, math.radians(30.0)), np.full(1, math.radians(45.0)), np.zeros(1, dtype=np.int32),
+                    seed=seed, _mesh=jerusalem_cross(cell=cell))
 
 
 @dataclass

@@ -167,3 +167,46 @@ def icosphere(radius: float, level: int) -> SurfaceMesh:
     flip = np.einsum("ij,ij->i", nrm, p.mean(1)) < 0
     tri[flip] = tri[flip][:, [0, 2, 1]]
     return SurfaceMesh(vert, tri, rwg_table(tri))
+
+
+def jerusalem_cross(arm: float = 0.4, width: float = 0.04, cap_len: float = 0.2, cap_w: float = 0.02,
+                    cell: float = 0.01) -> SurfaceMesh:
+    """Zero-thickness Jerusalem-cross plate in the plane z = 0, normal +z: two crossed
+    arms (arm x width) with an end cap (cap_w along the arm, cap_len across it) centred
+    on each arm end.  The shape is rasterised on square cells of side `cell` centred on
+    the origin (a cell is kept when its centre lies in the shape) and every kept cell
+    is split in two triangles as in square_plate."""
+    half = int(round(0.5 * (arm + cap_w) / cell)) + 1
+    centres = (np.arange(-half, half) + 0.5) * cell
+
+    def inside(x: float, y: float) -> bool:
+        eps = 1e-9
+        if abs(y) <= 0.5 * width + eps and abs(x) <= 0.5 * arm + eps:
+            return True
+        if abs(x) <= 0.5 * width + eps and abs(y) <= 0.5 * arm + eps:
+            return True
+        for s in (-1.0, 1.0):
+            if abs(x - s * 0.5 * arm) <= 0.5 * cap_w + eps and abs(y) <= 0.5 * cap_len + eps:
+                return True
+            if abs(y - s * 0.5 * arm) <= 0.5 * cap_w + eps and abs(x) <= 0.5 * cap_len + eps:
+                return True
+        return False
+
+    n = 2 * half
+    keep = [(i, j) for j in range(n) for i in range(n) if inside(centres[i], centres[j])]
+    ids: dict[tuple[int, int], int] = {}
+    verts = []
+
+    def P(i: int, j: int) -> int:
+        if (i, j) not in ids:
+            ids[(i, j)] = len(verts)
+            verts.append(((i - half) * cell, (j - half) * cell, 0.0))
+        return ids[(i, j)]
+
+    tris = []
+    for i, j in keep:
+        p00, p10, p11, p01 = P(i, j), P(i + 1, j), P(i + 1, j + 1), P(i, j + 1)
+        tris.append((p00, p10, p11))
+        tris.append((p00, p11, p01))
+    tri = np.asarray(tris, dtype=np.int32)
+    return SurfaceMesh(np.asarray(verts, dtype=np.float64), tri, rwg_table(tri))

@@ -1,0 +1,94 @@
+"""Standard AIM-MoM on the original scatterers with the same kernels: an array of PEC
+Jerusalem crosses (each element's own open surface meshed) solved as G J = V
+(gmres system AIM_G_ONLY), against the oracle's AIM operator on the same mesh."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.excitation import plane_wave_rhs, radiated_field, rcs_db
+from oracle.gmres import gmres as oracle_gmres
+from oracle.system import OracleOperator
+from synth import standard_mom_workload
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def case():
+    """3 x 3 crosses meshed on 0.02-wavelength squares (368 RWG each), oracle solution."""
+    wl = standard_mom_workload(px=3, py=3, cell=0.02)
+    o = OracleOperator(wl, M=-np.eye(wl.n_rwg, dtype=np.complex128)[None])
+    V = plane_wave_rhs(o.geo, wl.elem_center(), wl.theta[0], wl.phi[0], wl.pol[0], wl.k)
+    xo, info = oracle_gmres(o.g_apply, V, restart=50, tol=1e-11, max_iters=5000)
+    assert info["converged"]
+    return wl, o, xo, info
+
+
+def make_op(wl):
+    from paper_1712_02443_amd import AimOperator
+    op = AimOperator.from_workload(wl)
+    return op
+
+
+def test_standard_mom_fp64_matches_oracle(torch, case):
+    from paper_1712_02443_amd import AIM_G_ONLY
+    wl, o, xo, info = case
+    say(f"standard MoM {wl.name} {wl.px}x{wl.py}, {wl.n_rwg} RWG per element")
+    op = make_op(wl)
+    b = op.plane_wave_rhs(wl.theta, wl.phi, wl.pol)
+    x, st, code = op.gmres(b, restart=50, tol=1e-11, max_iters=5000, system=AIM_G_ONLY)
+    assert code == 0 and st[0]["converged"]
+    assert np.abs(x.cpu().numpy()[0] - xo).max() <= 1e-8 * np.abs(xo).max()
+    _, st6, _ = op.gmres(b, restart=50, tol=1e-6, max_iters=5000, system=AIM_G_ONLY)
+    _, info6 = oracle_gmres(o.g_apply, b.cpu().numpy()[0], restart=50, tol=1e-6, max_iters=5000)
+    assert abs(st6[0]["iters"] - info6["iters"]) <= 2
+    op.close()
+
+
+def test_standard_mom_mixed_and_far_field(torch, case):
+    from paper_1712_02443_amd import AIM_G_ONLY, AIM_MIXED
+    wl, o, xo, info = case
+    op = make_op(wl)
+    b = op.plane_wave_rhs(wl.theta, wl.phi, wl.pol)
+    x, st, code = op.gmres(b, restart=50, tol=1e-8, max_iters=5000, precision=AIM_MIXED, system=AIM_G_ONLY)
+    assert code == 0 and st[0]["converged"]
+    assert np.abs(x.cpu().numpy()[0] - xo).max() <= 1e-5 * np.abs(xo).max()
+    th = np.linspace(0, np.pi, 73)
+    rh = np.concatenate([np.stack([np.sin(th), np.zeros_like(th), np.cos(th)], 1),
+                         np.stack([np.zeros_like(th), np.sin(th), np.cos(th)], 1)])
+    E, db = op.far_field(x, rh, system=AIM_G_ONLY)
+    ref = radiated_field(o.geo, wl.elem_center(), xo, rh, wl.k, wl.eta)
+    db_o = rcs_db(ref)
+    keep = db_o > db_o.max() - 40.0
+    assert np.abs(db.cpu().numpy()[0] - db_o)[keep].max() <= 0.05
+    op.close()
+
+
+def test_standard_mom_block_jacobi(torch, case):
+    """Blocks built with M = -I and an empty D are G_self^-1: fewer iterations, same solution."""
+    from paper_1712_02443_amd import AIM_G_ONLY, AIM_PRECOND_BLOCK_JACOBI
+    wl, o, xo, info = case
+    op = make_op(wl)
+    op.set_macromodels(-np.eye(wl.n_rwg, dtype=np.complex128)[None])
+    op.set_dmatrix(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.complex128))
+    op.build_preconditioner()
+    b = op.plane_wave_rhs(wl.theta, wl.phi, wl.pol)
+    x, st, code = op.gmres(b, restart=50, tol=1e-11, max_iters=5000, system=AIM_G_ONLY,
+                           precond=AIM_PRECOND_BLOCK_JACOBI)
+    assert code == 0 and st[0]["iters"] < info["iters"]
+    assert np.abs(x.cpu().numpy()[0] - xo).max() <= 1e-8 * np.abs(xo).max()
+    op.close()

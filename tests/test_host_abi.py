@@ -114,10 +114,10 @@ def test_device_calls_on_host_op_report_state(lib):
     assert lib.macro_apply(op._op, buf, ctypes.c_void_p(2), 1, 0, None) == _lib.AIM_ESTATE
     assert lib.aim_matvec(None, buf, buf, 1, 0, 0, None) == _lib.AIM_EINVAL
     rh = np.array([0.0, 0.0, 1.0])
-    assert lib.aim_far_field(op._op, buf, 1, 1, rh.ctypes.data_as(_lib._f64p), buf, None, None) == _lib.AIM_ESTATE
-    assert lib.aim_far_field(op._op, buf, 1, 0, rh.ctypes.data_as(_lib._f64p), buf, None, None) == _lib.AIM_EINVAL
+    assert lib.aim_far_field(op._op, buf, 1, 1, rh.ctypes.data_as(_lib._f64p), buf, None, 0, None) == _lib.AIM_ESTATE
+    assert lib.aim_far_field(op._op, buf, 1, 0, rh.ctypes.data_as(_lib._f64p), buf, None, 0, None) == _lib.AIM_EINVAL
     rh[0] = np.nan
-    assert lib.aim_far_field(op._op, buf, 1, 1, rh.ctypes.data_as(_lib._f64p), buf, None, None) == _lib.AIM_EINVAL
+    assert lib.aim_far_field(op._op, buf, 1, 1, rh.ctypes.data_as(_lib._f64p), buf, None, 0, None) == _lib.AIM_EINVAL
     op.close()
 
 
