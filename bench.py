@@ -161,6 +161,8 @@ def main() -> int:
     ap.add_argument("--no-precond", action="store_true", help="skip the block-Jacobi preconditioned solves")
     ap.add_argument("--no-standard-mom", action="store_true",
                     help="skip the standard AIM-MoM solves on the original Jerusalem-cross surfaces")
+    ap.add_argument("--no-multi-rhs", action="store_true",
+                    help="skip the multi-RHS solves (16x16 plates with 64 RHS, 64x64 crosses with 8 RHS)")
     ap.add_argument("--profile-products", type=int, default=0,
                     help="only run this many FP32 and FP64 products and a 512 MiB device copy "
                          "(the copy calibrates hardware byte counters), then exit")
@@ -348,6 +350,36 @@ def main() -> int:
         del ops
         out["standard_mom"] = sm
         print(f"[bench] standard MoM: {sm}", file=sys.stderr, flush=True)
+
+    if not args.no_multi_rhs:
+        # many incidences as one block: every right-hand side in every launch
+        mr = {}
+        for idx in (2, 4):
+            wm = make_workload(idx)
+            opm = AimOperator.from_workload(wm)
+            opm.set_macromodels(wm.macromodels())
+            opm.set_dmatrix(*wm.d_matrix())
+            bm = opm.plane_wave_rhs(wm.theta, wm.phi, wm.pol)
+            ent = {"unknowns_per_rhs": wm.n_unknowns, "nrhs": wm.nrhs, "restart": wm.restart}
+            for prec, tag in ((AIM_MIXED, "mixed"), (AIM_FP64, "fp64")):
+                mkw = dict(restart=wm.restart, tol=args.tol, max_iters=5000, check_every=5, precision=prec)
+                opm.gmres(bm, **mkw)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                _, stm, cm = opm.gmres(bm, **mkw)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t
+                ent[f"{tag}_solve_ms"] = dt * 1e3
+                ent[f"{tag}_rhs_matvecs_per_s"] = sum(q["matvecs"] for q in stm) / dt
+                ent[f"{tag}_max_iters"] = max(q["iters"] for q in stm)
+                ent[f"{tag}_all_converged"] = cm == 0
+            ent["mixed_vs_fp64_solve_speedup"] = ent["fp64_solve_ms"] / ent["mixed_solve_ms"]
+            mr[wm.name] = ent
+            opm.close()
+            del opm
+            torch.cuda.empty_cache()
+        out["multi_rhs"] = mr
+        print(f"[bench] multi-RHS: {mr}", file=sys.stderr, flush=True)
 
     # standalone products
     x64 = torch.from_numpy(wl.test_vectors(1)).to("cuda")
