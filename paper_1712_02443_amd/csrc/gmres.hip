@@ -753,7 +753,9 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
   // iterations run past convergence.  Each check extrapolates every running residual
   // estimate geometrically from the previous check and places the next check where
   // the slowest is predicted to pass its threshold (at most check_every ahead).
-  std::vector<double> est_prev(R);
+  // The first check of a later cycle is placed from the rate the previous cycle
+  // reached (its restart usually sits just above the threshold).
+  std::vector<double> est_prev(R), rate_last(R, 0.0);
   std::vector<int> j_prev(R);
   bool x_zero = !o.x0_given;
   for (;;) {
@@ -795,6 +797,20 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
       j_prev[r] = 0;
     }
     int j_end = 0, next_check = std::min(check, budget_max);
+    {
+      bool known = true;
+      int need_max = 1;
+      for (int r = 0; r < R; ++r) {
+        if (!active[r]) continue;
+        if (!(rate_last[r] < 0)) {
+          known = false;
+          break;
+        }
+        const int need = int(std::ceil(std::log(hs[4 * r + 1] / hs[4 * r]) / rate_last[r]));
+        need_max = std::max(need_max, std::min(std::max(need, 1), check));
+      }
+      if (known) next_check = std::min(next_check, need_max);
+    }
     for (int j = 0; j < budget_max; ++j) {
       const cplx<Tb>* uj = V + int64_t(j) * R * n;
       cplx<Tb>* unext = V + int64_t(j + 1) * R * n;
@@ -840,6 +856,7 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
           if (est > 0 && est < est_prev[r] && thr > 0) {
             const double rate = std::log(est / est_prev[r]) / double(j_end - j_prev[r]);
             need = int(std::ceil(std::log(thr / est) / rate));
+            rate_last[r] = rate;
           }
           ahead = std::max(ahead, std::min(std::max(need, 1), check));
           est_prev[r] = est;
