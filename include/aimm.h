@@ -258,7 +258,8 @@ int aim_get_near(const aim_op* op, int32_t* rows, int32_t* offs, int32_t* cols, 
                  int32_t* offsets);
 
 /* Device bytes an op of this array would hold, Krylov basis included, for admission
- * decisions; host only. */
+ * decisions; host only.  Not included: the block-Jacobi blocks (aim_build_preconditioner,
+ * about 3 n_types N^2 x 16 bytes) and the far-field workspace, allocated when first used. */
 size_t aim_footprint_bytes(const aim_surface* surface, const aim_array* array, int32_t nrhs,
                            int32_t restart, int32_t precision);
 
