@@ -144,11 +144,14 @@ int macro_apply(aim_op* op, const void* x, void* u, int32_t nrhs, int32_t precis
 int aim_matvec(aim_op* op, const void* x, void* y, int32_t nrhs, int32_t precision,
                int32_t flags, void* stream);
 
-/* Kernel timing of the full product with HIP events on `stream`: one warm-up, then
- * reps products; ms[k] receives the mean duration in milliseconds of kernel k:
+/* Kernel timing of the full product with HIP events on `stream`: after one full
+ * product, each kernel is launched once untimed and then reps times back to back
+ * between two events; ms[k] receives the mean duration in milliseconds of kernel k:
  * 0 macromodel GEMM, 1 projection (step (i)), 2 forward FFT along y, 3 FFT along x
  * with the kernel-spectrum product, 4 inverse FFT along y (step (ii)), 5 pre-corrected
  * near field, 6 interpolation (step (iii)) fused with D and the final combination.
+ * The x pass writes to a temporary device buffer of the spectrum pass size (allocated
+ * and freed inside the call; AIM_ENOMEM if that fails).  y holds the product on return.
  * ms: host [7].  Synchronises the stream. */
 int aim_time_kernels(aim_op* op, const void* x, void* y, int32_t nrhs, int32_t precision,
                      int32_t reps, double* ms, void* stream);

@@ -145,10 +145,12 @@ class AimOperator:
 
     KERNELS = ("macro_gemm", "project", "fft_y_fwd", "fft_x_conv", "fft_y_inv", "near_field", "interp_d")
 
-    def time_kernels(self, x, precision=AIM_FP64, reps=20, stream=None) -> dict:
-        """Mean per-kernel duration (ms) of the full product, from HIP events on the stream."""
+    def time_kernels(self, x, precision=AIM_FP64, reps=20, stream=None, out=None) -> dict:
+        """Mean per-kernel duration (ms) of the full product: each kernel launched reps
+        times back to back between HIP events on the stream.  out (optional) receives
+        the product."""
         R = self._check_vec(x, precision)
-        y = self._torch.empty_like(x)
+        y = self._torch.empty_like(x) if out is None else out
         ms = np.zeros(7)
         check(self.lib.aim_time_kernels(self._op, _dev_ptr(x), _dev_ptr(y), R, precision, int(reps),
                                         ms.ctypes.data_as(_lib._f64p), _stream(self._torch, stream)))

@@ -1123,23 +1123,32 @@ hipError_t launch_convolve4_z(const cplx<T>* Q, cplx<T>* Phi, cplx<T>* S, const 
   auto threads = [](int lines, int l1, int l2) { return unsigned((lines * std::max(l1, l2) + 63) / 64 * 64); };
   if (threads(a.B * a.nz, LX1, LX2) > 512 || threads(a.nz, LY1, LY2) > 512) return hipErrorInvalidConfiguration;
   size_t lds = sizeof(cplx<T>) * (size_t(Ly) + size_t(a.nz) * f4_ld<LY1, LY2>());
-  hipLaunchKernelGGL((k_fft4_y_fwd<T, LY1, LY2, NZ>), dim3(planes), dim3(threads(a.nz, LY1, LY2)), lds, s, Q, S, a.ny,
-                     a.nz, reinterpret_cast<const cplx<T>*>(a.tw_y));
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  if (a.passes & 1) {
+    hipLaunchKernelGGL((k_fft4_y_fwd<T, LY1, LY2, NZ>), dim3(planes), dim3(threads(a.nz, LY1, LY2)), lds, s, Q, S,
+                       a.ny, a.nz, reinterpret_cast<const cplx<T>*>(a.tw_y));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (ev) (void)hipEventRecord(ev[0], s);
-  const int nkb = Ly / a.B, nblocks = a.R * 4 * nkb;
-  lds = sizeof(cplx<T>) * (size_t(Lx) + size_t(a.B) * a.nz * f4_ld<LX1, LX2>());
-  hipLaunchKernelGGL((k_fft4_x<T, LX1, LX2, NZ>), dim3((nblocks + kXcds - 1) / kXcds * kXcds),
-                     dim3(threads(a.B * a.nz, LX1, LX2)), lds, s, S, S, a.nx, Ly, a.nz, a.B, nblocks,
-                     reinterpret_cast<const cplx<T>*>(a.tw_x), reinterpret_cast<const cplx<T>*>(a.gt));
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (a.passes & 2) {
+    const int nkb = Ly / a.B, nblocks = a.R * 4 * nkb;
+    cplx<T>* xo = a.x_out ? static_cast<cplx<T>*>(a.x_out) : S;
+    lds = sizeof(cplx<T>) * (size_t(Lx) + size_t(a.B) * a.nz * f4_ld<LX1, LX2>());
+    hipLaunchKernelGGL((k_fft4_x<T, LX1, LX2, NZ>), dim3((nblocks + kXcds - 1) / kXcds * kXcds),
+                       dim3(threads(a.B * a.nz, LX1, LX2)), lds, s, S, xo, a.nx, Ly, a.nz, a.B, nblocks,
+                       reinterpret_cast<const cplx<T>*>(a.tw_x), reinterpret_cast<const cplx<T>*>(a.gt));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (ev) (void)hipEventRecord(ev[1], s);
-  lds = sizeof(cplx<T>) * (size_t(Ly) + size_t(a.nz) * f4_ld<LY1, LY2>());
-  hipLaunchKernelGGL((k_fft4_y_inv<T, LY1, LY2, NZ>), dim3(planes), dim3(threads(a.nz, LY1, LY2)), lds, s, S, Phi, a.ny,
-                     a.nz, reinterpret_cast<const cplx<T>*>(a.tw_y));
-  return hipGetLastError();
+  if (a.passes & 4) {
+    lds = sizeof(cplx<T>) * (size_t(Ly) + size_t(a.nz) * f4_ld<LY1, LY2>());
+    hipLaunchKernelGGL((k_fft4_y_inv<T, LY1, LY2, NZ>), dim3(planes), dim3(threads(a.nz, LY1, LY2)), lds, s, S, Phi,
+                       a.ny, a.nz, reinterpret_cast<const cplx<T>*>(a.tw_y));
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 template <typename T, int LX1, int LX2, int LY1, int LY2>
@@ -1172,23 +1181,32 @@ hipError_t launch_convolve(const cplx<T>* Q, cplx<T>* Phi, cplx<T>* S, const Con
   }
   const int planes = a.R * 4 * a.nx;
   size_t lds = sizeof(cplx<T>) * size_t(a.Py.L) * (1 + a.nz);
-  hipLaunchKernelGGL(k_fft_y_fwd<T>, dim3(planes), dim3(256), lds, s, Q, S, a.ny, a.nz, a.Py,
-                     reinterpret_cast<const cplx<T>*>(a.tw_y));
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  if (a.passes & 1) {
+    hipLaunchKernelGGL(k_fft_y_fwd<T>, dim3(planes), dim3(256), lds, s, Q, S, a.ny, a.nz, a.Py,
+                       reinterpret_cast<const cplx<T>*>(a.tw_y));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (ev) (void)hipEventRecord(ev[0], s);
-  const int nkb = a.Py.L / a.B;
-  lds = sizeof(cplx<T>) * size_t(a.Px.L) * (1 + a.B * a.nz);
-  hipLaunchKernelGGL((k_fft_x<T, 0>), dim3(a.R * 4 * nkb), dim3(256), lds, s, S, S, a.nx, a.Py.L, a.nz, a.B,
-                     a.Px, reinterpret_cast<const cplx<T>*>(a.tw_x), reinterpret_cast<const cplx<T>*>(a.gt),
-                     a.rev_x, a.rev_y);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (a.passes & 2) {
+    const int nkb = a.Py.L / a.B;
+    cplx<T>* xo = a.x_out ? static_cast<cplx<T>*>(a.x_out) : S;
+    lds = sizeof(cplx<T>) * size_t(a.Px.L) * (1 + a.B * a.nz);
+    hipLaunchKernelGGL((k_fft_x<T, 0>), dim3(a.R * 4 * nkb), dim3(256), lds, s, S, xo, a.nx, a.Py.L, a.nz, a.B,
+                       a.Px, reinterpret_cast<const cplx<T>*>(a.tw_x), reinterpret_cast<const cplx<T>*>(a.gt),
+                       a.rev_x, a.rev_y);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (ev) (void)hipEventRecord(ev[1], s);
-  lds = sizeof(cplx<T>) * size_t(a.Py.L) * (1 + a.nz);
-  hipLaunchKernelGGL(k_fft_y_inv<T>, dim3(planes), dim3(256), lds, s, S, Phi, a.ny, a.nz, a.Py,
-                     reinterpret_cast<const cplx<T>*>(a.tw_y));
-  return hipGetLastError();
+  if (a.passes & 4) {
+    lds = sizeof(cplx<T>) * size_t(a.Py.L) * (1 + a.nz);
+    hipLaunchKernelGGL(k_fft_y_inv<T>, dim3(planes), dim3(256), lds, s, S, Phi, a.ny, a.nz, a.Py,
+                       reinterpret_cast<const cplx<T>*>(a.tw_y));
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 template <typename T>

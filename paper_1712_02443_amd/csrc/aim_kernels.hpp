@@ -35,6 +35,8 @@ struct ConvArgs {
   const void* gt;
   const int* rev_x;
   const int* rev_y;
+  int passes;        // bit 0: forward y, bit 1: x with the spectrum product, bit 2: inverse y
+  void* x_out;       // target of the x pass; nullptr: in place in S
 };
 
 constexpr int kNearGroupDev = 16;  // rows per matrix-core near-field group

@@ -125,6 +125,19 @@ def test_full_product(torch, case, prec):
     assert rel(Y, ref) < TOL[prec]
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_kernel_timing_leaves_the_product(torch, prec):
+    """aim_time_kernels times every kernel and still returns the full product."""
+    wl, op, o = make_pair(torch, CASES[2][0], **CASES[2][1])
+    say(f"kernel timing {wl.name} prec={prec} rhs={wl.nrhs}")
+    X = wl.test_vectors()
+    x = to_dev(torch, X, prec)
+    y = torch.empty_like(x)
+    t = op.time_kernels(x, precision=prec, reps=3, out=y)
+    assert set(t) == set(op.KERNELS) and all(v > 0 for v in t.values())
+    assert rel(to_host(y), o.matvec(X)) < TOL[prec]
+
+
 @pytest.mark.parametrize("case", [CASES[0], CASES[2]])
 def test_radix_stage_fft_path(torch, case, monkeypatch):
     """The radix-stage FFT passes (used for lengths without a register-DFT
