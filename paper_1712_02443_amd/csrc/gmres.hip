@@ -91,24 +91,23 @@ __device__ __forceinline__ void load_batch(const cplx<Tb>* __restrict__ V, int i
   }
 }
 
-// Lane exchanges without the LDS crossbar.  xchg32 / xchg16: the value of the lane
-// whose bit 5 / bit 4 differs (v_permlane32_swap / v_permlane16_swap exchange the
-// upper and lower halves of each 64- / 32-lane group).  mirror16 / mirror8 / qperm:
-// DPP row_mirror (lane l <-> 15 - l in each row of 16), row_half_mirror (l <-> 7 - l
-// in each group of 8) and quad permutations, all on the vector ALU.
-__device__ __forceinline__ double xchg32(double v, int lane) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  const auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-  const auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-  const bool up_half = lane & 32;
-  return __hiloint2double(up_half ? ph[0] : ph[1], up_half ? pl[0] : pl[1]);
+// Lane exchanges without the LDS crossbar.  fold32(a, b): lanes 0-31 receive
+// a[l] + a[l + 32] and lanes 32-63 receive b[l - 32] + b[l]; fold16(a, b): in each
+// 32-lane half, lanes with bit 4 clear receive a[l] + a[l + 16] and lanes with it set
+// b[l - 16] + b[l].  v_permlane32_swap (v_permlane16_swap) exchanges the upper lanes
+// (odd rows of 16) of its first operand with the lower lanes (even rows) of its second,
+// so one swap of (a, b) leaves each lane holding both terms of its sum.  dpp<CTRL>: a
+// DPP lane permutation on the vector ALU (row_mirror: lane l <-> 15 - l in each row of
+// 16; row_half_mirror: l <-> 7 - l in each group of 8; quad permutations).
+__device__ __forceinline__ double fold32(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
 }
-__device__ __forceinline__ double xchg16(double v, int lane) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  const auto pl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-  const auto ph = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-  const bool odd_row = lane & 16;
-  return __hiloint2double(odd_row ? ph[0] : ph[1], odd_row ? pl[0] : pl[1]);
+__device__ __forceinline__ double fold16(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
@@ -124,19 +123,13 @@ constexpr int kRowMirror = 0x140, kHalfMirror = 0x141, kQuadSwap2 = 0x4E, kQuadS
 // in the lanes whose bits 5..3 spell q; three more exchanges within each group of 8
 // lanes finish the sum.  The summation order is fixed.
 __device__ __forceinline__ double wave_sum8(double (&x)[8], int lane) {
-  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+  const bool b3 = lane & 8;
   double y[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const double send = b5 ? x[q] : x[q + 4], keep = b5 ? x[q + 4] : x[q];
-    y[q] = keep + xchg32(send, lane);
-  }
+  for (int q = 0; q < 4; ++q) y[q] = fold32(x[q], x[q + 4]);
   double z[2];
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const double send = b4 ? y[q] : y[q + 2], keep = b4 ? y[q + 2] : y[q];
-    z[q] = keep + xchg16(send, lane);
-  }
+  for (int q = 0; q < 2; ++q) z[q] = fold16(y[q], y[q + 2]);
   double t;
   {
     const double send = b3 ? z[0] : z[1], keep = b3 ? z[1] : z[0];
