@@ -655,9 +655,9 @@ __global__ void __launch_bounds__(256) k_near_mfma(const cplx<T>* __restrict__ u
 // staged in LDS; every basis gathers its (N_O+1)^3 nodes per psi from LDS.  MODE 0: y = D x - (v + nf); 1: y = v + nf;
 // 2: y = v, with v = -j k eta0 [sum_{x,y,z} I_psi Phi_psi - k^-2 I_phi Phi_phi].
 template <typename T, int MODE, int QS>
-__global__ void __launch_bounds__(256) k_interp(const cplx<T>* __restrict__ Phi, const cplx<T>* __restrict__ nf,
-                                                const cplx<T>* __restrict__ x, cplx<T>* __restrict__ y, InterpArgs a,
-                                                const T* __restrict__ Wt, const cplx<T>* __restrict__ d_val) {
+__global__ void __launch_bounds__(sizeof(T) == sizeof(float) ? 1024 : 512)
+    k_interp(const cplx<T>* __restrict__ Phi, const cplx<T>* __restrict__ nf, const cplx<T>* __restrict__ x,
+             cplx<T>* __restrict__ y, InterpArgs a, const T* __restrict__ Wt, const cplx<T>* __restrict__ d_val) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* box = reinterpret_cast<cplx<T>*>(smem_raw);
   const int ntx = (a.px + a.TX - 1) / a.TX;
@@ -1229,7 +1229,10 @@ hipError_t launch_interp(int mode, const cplx<T>* Phi, const cplx<T>* nf, const 
                          const InterpArgs& a, const T* Wt, const cplx<T>* d_val, hipStream_t s) {
   const int tiles = ((a.px + a.TX - 1) / a.TX) * ((a.py + a.TY - 1) / a.TY);
   const size_t lds = interp_lds_bytes(a, sizeof(cplx<T>));
-  const dim3 g(tiles, a.R), b(256);
+  // one thread per basis function in FP32 (no serial loop over a tile's rows); FP64,
+  // with twice the registers and LDS per block, ran fastest at 512 (measured, N = 648)
+  const int bs = std::min(sizeof(T) == sizeof(float) ? 1024 : 512, (a.N + 63) / 64 * 64);
+  const dim3 g(tiles, a.R), b(bs);
 #define AIM_INTERP(M, QQ) hipLaunchKernelGGL((k_interp<T, M, QQ>), g, b, lds, s, Phi, nf, x, y, a, Wt, d_val)
 #define AIM_INTERP_Q(M)                  \
   switch (a.q) {                        \
