@@ -174,8 +174,9 @@ def main() -> int:
         summarize_counters(*args.summarize_counters, command=args.counter_command)
         return 0
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(the path shards over right-hand sides or x-slabs, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path would shard over "
+              "right-hand sides, or over x-slabs of the grid with all-to-all exchanges around the x FFT pass)",
+              file=sys.stderr)
         return 2
 
     import numpy as np
