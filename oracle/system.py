@@ -22,7 +22,7 @@ from .geometry import rwg_geometry
 
 class OracleOperator:
     def __init__(self, wl: Workload, near_mode: str = "offset", g0: complex = 0.0, pad=None,
-                 M: np.ndarray | None = None):
+                 M: np.ndarray | None = None, near: bool = True):
         self.wl = wl
         mesh = wl.surface
         self.geo = rwg_geometry(mesh.vert, mesh.tri, mesh.rwg)
@@ -36,7 +36,11 @@ class OracleOperator:
         r, c, v = wl.d_matrix()
         self.D = sp.csr_matrix((v, (r, c)), shape=(self.nb, self.nb))
         self.near_mode = near_mode
-        self._build_near()
+        # near=False skips the (slow) pre-corrected near field for uses of the grid part
+        # alone; near_apply, g_apply and matvec then raise
+        self._near_built = near
+        if near:
+            self._build_near()
 
     # ---- near field -------------------------------------------------------------
     def _near_block(self, shift_a, ga, shift_b, gb):
@@ -97,6 +101,8 @@ class OracleOperator:
     @property
     def C(self):
         """The pre-corrected near-field matrix as one global CSR (built on first use)."""
+        if not self._near_built:
+            raise RuntimeError("operator built with near=False")
         if self._C is None:
             n = self.wl.n_elem * self.nb
             self._C = sp.csr_matrix((np.concatenate(self._vals),
@@ -122,6 +128,8 @@ class OracleOperator:
 
     def near_apply(self, u: np.ndarray, by_blocks: bool | None = None) -> np.ndarray:
         """C u; per-offset blocks for arrays too large for one global sparse matrix."""
+        if not self._near_built:
+            raise RuntimeError("operator built with near=False")
         wl, nb = self.wl, self.nb
         if by_blocks is None:
             by_blocks = self.near_mode == "offset" and wl.n_elem * nb > 200_000
@@ -173,6 +181,8 @@ class OracleOperator:
         """
         if self.near_mode != "offset":
             raise ValueError("matvec_rows needs near_mode='offset'")
+        if not self._near_built:
+            raise RuntimeError("operator built with near=False")
         wl, nb = self.wl, self.nb
         rows = np.asarray(rows, dtype=np.int64)
         u = self.macro_apply(x)

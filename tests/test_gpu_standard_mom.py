@@ -92,3 +92,23 @@ def test_standard_mom_block_jacobi(torch, case):
     assert code == 0 and st[0]["iters"] < info["iters"]
     assert np.abs(x.cpu().numpy()[0] - xo).max() <= 1e-8 * np.abs(xo).max()
     op.close()
+
+
+def test_far_product_elements_over_1024_rwg(torch):
+    """Elements with more RWG functions (1,068 per cross) than an FP32 interpolation
+    workgroup has threads, so the kernel loops over its rows: the grid part of G
+    (steps (i)-(iii), aim_matvec with AIM_FAR_ONLY) against the oracle in both precisions."""
+    from paper_1712_02443_amd import AIM_FAR_ONLY, AIM_FP64, AIM_MIXED
+    wl = standard_mom_workload(px=1, py=2, cell=0.011)
+    assert wl.n_rwg > 1024
+    say(f"far product {wl.name} {wl.px}x{wl.py}, {wl.n_rwg} RWG per element")
+    o = OracleOperator(wl, M=-np.eye(wl.n_rwg, dtype=np.complex128)[None], near=False)
+    X = wl.test_vectors(1)
+    ref = o.far_field(X[0])
+    op = make_op(wl)
+    for prec, dt, tol in ((AIM_FP64, torch.complex128, 1e-12), (AIM_MIXED, torch.complex64, 1e-5)):
+        y = op.matvec(torch.from_numpy(X).to(device="cuda", dtype=dt), precision=prec, flags=AIM_FAR_ONLY)
+        err = float(np.abs(y.cpu().numpy()[0] - ref).max() / np.abs(ref).max())
+        say(f"  precision {prec}: rel err {err:.2e}")
+        assert err <= tol
+    op.close()

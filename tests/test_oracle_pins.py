@@ -487,3 +487,17 @@ def test_efie_sphere_matches_mie_and_converges(sphere_solutions):
     err = [np.abs(s - ref).max() for s in sols]
     assert err[0] < 0.5
     assert err[1] < 0.5 * err[0]
+
+
+def test_oracle_without_near_field_keeps_the_grid_part():
+    """near=False only skips the near-field build: the grid part is bitwise the same,
+    and every use of the near field raises."""
+    wl = make_workload(0)
+    full = OracleOperator(wl)
+    far = OracleOperator(wl, near=False)
+    x = wl.test_vectors(1)[0]
+    assert np.array_equal(full.far_field(x), far.far_field(x))
+    with pytest.raises(RuntimeError):
+        far.near_apply(x)
+    with pytest.raises(RuntimeError):
+        far.matvec(x)
