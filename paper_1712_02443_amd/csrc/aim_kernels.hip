@@ -611,7 +611,7 @@ __global__ void __launch_bounds__(256) k_near_mfma(const cplx<T>* __restrict__ u
   const cplx<T>* Ag = grp_A + int64_t(g0) * kNearGroupDev;
   // three real products per complex step: re.re, im.im and (re + im).(re + im)
   typename M::acc_t accRR = {}, accII = {}, accSS = {};
-  constexpr int P = sizeof(T) == 4 ? 8 : 4;  // K-steps per batch; the next batch is loaded ahead
+  constexpr int P = 4;  // K-steps per batch; the next batch is loaded ahead (8 measured 2% slower in FP32)
   auto fetch = [&](int k, cplx<T>& av, cplx<T>& bv) {
     const int col = cols_s[k + kq];
     const bool ok = (vmask >> (col & 31)) & 1u;
