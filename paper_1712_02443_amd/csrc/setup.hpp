@@ -54,8 +54,8 @@ struct Setup {
 };
 
 constexpr int kNearGroup = 16;
-// group column counts are padded to a multiple of this: two K halves of whole 16-column prefetch batches
-constexpr int kNearColAlign = 32;
+// group column counts are padded to a multiple of this: four K quarters of whole 16-column prefetch batches
+constexpr int kNearColAlign = 64;
 constexpr int kNearColTail = 32;   // zero columns after the last group (one prefetch batch)
 
 // Throws std::invalid_argument with a message on bad input.
