@@ -762,9 +762,9 @@ __global__ void __launch_bounds__(sizeof(T) == sizeof(float) ? 1024 : 512)
 
 // ---- section III: block-diagonal macromodel product, grouped complex GEMM --------
 // U[:, c] = M_t X[:, c] for every column c = r * n_elem + m of an element of kind t,
-// on the matrix cores: each complex step is four real MFMAs (re*re - im*im,
-// re*im + im*re).  A 64 x 64 output tile per workgroup (2 x 2 waves); M_t and X
-// tiles are staged in LDS; the output is written element-fastest, uT[r][i][m].
+// on the matrix cores: each complex step is three real products (re.re, im.im and
+// (re + im).(re + im)), combined after the K loop; the output is written
+// element-fastest, uT[r][i][m].
 
 // Tile: 32 rows x kGemmCols columns per workgroup; its four waves split K in four
 // contiguous ranges and read their MFMA operands straight from global memory (A:
