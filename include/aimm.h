@@ -237,8 +237,9 @@ int aim_get_preconditioner(const aim_op* op, double* P);
 int precond_apply(aim_op* op, const void* x, void* y, int32_t nrhs, int32_t precision, void* stream);
 
 /* Far field of the solution's equivalent currents, for the radiation patterns and
- * bistatic RCS of section VI: with J = M x (section III; J = x when system is
- * AIM_G_ONLY, the surface currents of a standard MoM solve) and element m centred at c_m,
+ * bistatic RCS of section VI: with J = -M x (the equivalent currents J^ = T J =
+ * -T A^-1 B E^ of eq. Toperator and eq. JABE; J = x when system is AIM_G_ONLY, the
+ * surface currents of a standard MoM solve) and element m centred at c_m,
  *   E(r^) = -(j k eta / 4 pi) (I - r^ r^) . sum_m exp(j k r^ . c_m)
  *           sum_n J_{m,n} int Lambda_n(r) exp(j k r^ . r) dS,
  * the far-zone field E r exp(j k r) for unit incident amplitude, in FP64 (the sum over

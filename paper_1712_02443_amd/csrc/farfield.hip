@@ -1,8 +1,9 @@
 // Far field of the array's equivalent currents for many directions at once: the
 // directivity patterns and bistatic RCS that section VI reports for the solved arrays.
 //
-// With J = M x the equivalent electric currents of every element (section III; x the
-// solution of eq. finalsystem) and element m centred at c_m on the lattice,
+// With J = -M x the equivalent electric currents of every element (section III, eq.
+// Toperator with eq. JABE: J^ = T J = -T A^-1 B E^; x the solution E^ of eq.
+// finalsystem) and element m centred at c_m on the lattice,
 //   E(r^) = -(j k eta / 4 pi) (I - r^ r^) . sum_n F_n(r^) S(r^, n),
 //   S(r^, n) = sum_m exp(j k r^ . c_m) J[m][n],
 //   F_n(r^) = int Lambda_n(r) exp(j k r^ . r) dS   (element-local r),
@@ -140,6 +141,7 @@ __global__ void __launch_bounds__(256) k_ff_gemm(const cplx<double>* __restrict_
 __global__ void k_ff_finish(const cplx<double>* __restrict__ part, const double* __restrict__ rhat,
                             cplx<double>* __restrict__ E, double* __restrict__ rcs, int D, int R, int ntiles,
                             double keta) {
+  // keta carries the sign of the current: -k eta for J = -M x
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= R * D) return;
   const int r = t / D, d = t - r * D;
@@ -249,7 +251,7 @@ extern "C" int aim_far_field(aim_op* op, const void* x, int32_t nrhs, int32_t nd
   cplx<double>* Y = X + size_t(ndir) * px;
   cplx<double>* part = Y + size_t(ndir) * py;
   FF_HIP(hipMemcpyAsync(rd, rhat, size_t(ndir) * 3 * sizeof(double), hipMemcpyHostToDevice, s));
-  // currents J = M x (or x itself), element-fastest
+  // currents M x (negated in the last kernel) or x itself, element-fastest
   cplx<double>* uT = static_cast<cplx<double>*>(op->u);
   if (system == AIM_FULL) {
     GemmArgs ga = gemm_args_of(op, nrhs);
@@ -278,7 +280,7 @@ extern "C" int aim_far_field(aim_op* op, const void* x, int32_t nrhs, int32_t nd
   FF_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_ff_finish, dim3((nrhs * ndir + 255) / 256), dim3(256), 0, s, part, rd,
                      static_cast<cplx<double>*>(E), static_cast<double*>(rcs_db), ndir, nrhs, ntiles,
-                     op->arr.k * op->arr.eta);
+                     (system == AIM_FULL ? -1.0 : 1.0) * op->arr.k * op->arr.eta);
   FF_HIP(hipGetLastError());
   return AIM_OK;
 }

@@ -58,7 +58,7 @@ def test_far_field_matches_oracle(torch, case):
     E, rcs = E.cpu().numpy(), rcs.cpu().numpy()
     centers = wl.elem_center()
     for r in range(X.shape[0]):
-        ref = radiated_field(o.geo, centers, o.macro_apply(X[r]), rh, wl.k, wl.eta)
+        ref = radiated_field(o.geo, centers, -o.macro_apply(X[r]), rh, wl.k, wl.eta)
         assert rel(E[r], ref) < 1e-12
         keep = np.linalg.norm(ref, axis=1) > 1e-6 * np.abs(ref).max()
         assert np.max(np.abs(rcs[r][keep] - rcs_db(ref)[keep])) < 1e-9
@@ -85,7 +85,7 @@ def test_full_size_far_field(torch):
     x = wl.test_vectors(1)
     rh = directions(0)[::3]
     E, rcs = op.far_field(torch.from_numpy(x).to("cuda"), rh)
-    ref = radiated_field(o.geo, wl.elem_center(), o.macro_apply(x[0]), rh, wl.k, wl.eta)
+    ref = radiated_field(o.geo, wl.elem_center(), -o.macro_apply(x[0]), rh, wl.k, wl.eta)
     assert rel(E.cpu().numpy()[0], ref) < 1e-12
     op.close()
 
@@ -108,7 +108,7 @@ def test_device_rcs_of_mixed_solve_matches_fp64_oracle(torch, case):
     rh = np.concatenate([np.stack([np.sin(th), np.zeros_like(th), np.cos(th)], 1),
                          np.stack([np.zeros_like(th), np.sin(th), np.cos(th)], 1)])
     _, db_dev = op.far_field(xm, rh)
-    db_o = rcs_db(radiated_field(o.geo, wl.elem_center(), o.macro_apply(xo), rh, wl.k, wl.eta))
+    db_o = rcs_db(radiated_field(o.geo, wl.elem_center(), -o.macro_apply(xo), rh, wl.k, wl.eta))
     keep = db_o > db_o.max() - 40.0
     assert keep.sum() > 60
     assert np.max(np.abs(db_dev.cpu().numpy()[0] - db_o)[keep]) <= 0.05

@@ -253,8 +253,8 @@ def test_mixed_solve_rcs_matches_fp64_oracle(torch, case):
     rhat = np.concatenate([np.stack([np.sin(th), np.zeros_like(th), np.cos(th)], 1),
                            np.stack([np.zeros_like(th), np.sin(th), np.cos(th)], 1)])
     centers = wl.elem_center()
-    db_m = rcs_db(radiated_field(o.geo, centers, o.macro_apply(to_host(xm)[0]), rhat, wl.k, wl.eta))
-    db_o = rcs_db(radiated_field(o.geo, centers, o.macro_apply(xo), rhat, wl.k, wl.eta))
+    db_m = rcs_db(radiated_field(o.geo, centers, -o.macro_apply(to_host(xm)[0]), rhat, wl.k, wl.eta))
+    db_o = rcs_db(radiated_field(o.geo, centers, -o.macro_apply(xo), rhat, wl.k, wl.eta))
     keep = db_o > db_o.max() - 40.0
     assert keep.sum() > 60
     assert np.max(np.abs(db_m - db_o)[keep]) <= 0.05
