@@ -252,6 +252,20 @@ int precond_apply(aim_op* op, const void* x, void* y, int32_t nrhs, int32_t prec
 int aim_far_field(aim_op* op, const void* x, int32_t nrhs, int32_t ndir, const double* rhat, void* E,
                   void* rcs_db, int32_t system, void* stream);
 
+/* aim_far_field without any device allocation, for callers that cannot allocate (code
+ * under HIP graph capture, serving loops with a fixed memory budget): the same kernels
+ * and results, with the directions, phase tables and per-tile partials in a
+ * library-owned scratch array of 16 MiB per GPU (held until the process ends) instead
+ * of an op workspace.  The workspace a call needs is
+ *   256-byte-rounded 24 ndir + 16 ndir (px + py) + 48 ceil(N / 32) nrhs ndir  bytes;
+ * a call needing more returns AIM_EINVAL (nothing modified).  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams, other ops,
+ * other host threads) race and must be ordered by the caller.  The op's own device
+ * buffers, allocated when it was built, serve as before.  Other arguments, errors and
+ * results as aim_far_field. */
+int aim_far_field_noalloc(aim_op* op, const void* x, int32_t nrhs, int32_t ndir, const double* rhat, void* E,
+                          void* rcs_db, int32_t system, void* stream);
+
 /* Sizes of the op (host only, no device work). */
 int aim_get_info(const aim_op* op, aim_info* info);
 

@@ -185,17 +185,24 @@ class AimOperator:
                                           po.ctypes.data_as(_lib._i32p), R, _dev_ptr(b), _stream(self._torch, stream)))
         return b
 
-    def far_field(self, x, rhat, system=AIM_FULL, stream=None):
+    def far_field(self, x, rhat, system=AIM_FULL, stream=None, out=None, noalloc=False):
         """Far-zone field (nrhs, ndir, 3) complex128 and RCS in dB (nrhs, ndir) of the
         solutions x (device complex128) along the unit directions rhat (ndir, 3); the
-        currents are M x (AIM_FULL) or x (AIM_G_ONLY)."""
+        currents are -M x (AIM_FULL) or x (AIM_G_ONLY).  out = (E, rcs) reuses output
+        tensors; noalloc calls aim_far_field_noalloc (library scratch, no allocation)."""
         R = self._check_vec(x, AIM_FP64)
         rh = np.ascontiguousarray(rhat, dtype=np.float64).reshape(-1, 3)
         D = rh.shape[0]
-        E = self._torch.empty((R, D, 3), dtype=self._torch.complex128, device=x.device)
-        rcs = self._torch.empty((R, D), dtype=self._torch.float64, device=x.device)
-        check(self.lib.aim_far_field(self._op, _dev_ptr(x), R, D, rh.ctypes.data_as(_lib._f64p), _dev_ptr(E),
-                                     _dev_ptr(rcs), int(system), _stream(self._torch, stream)))
+        if out is None:
+            E = self._torch.empty((R, D, 3), dtype=self._torch.complex128, device=x.device)
+            rcs = self._torch.empty((R, D), dtype=self._torch.float64, device=x.device)
+        else:
+            E, rcs = out
+            if tuple(E.shape) != (R, D, 3) or tuple(rcs.shape) != (R, D):
+                raise ValueError("out tensors have the wrong shape")
+        fn = self.lib.aim_far_field_noalloc if noalloc else self.lib.aim_far_field
+        check(fn(self._op, _dev_ptr(x), R, D, rh.ctypes.data_as(_lib._f64p), _dev_ptr(E), _dev_ptr(rcs),
+                 int(system), _stream(self._torch, stream)))
         return E, rcs
 
     def gmres(self, b, x=None, *, restart=50, tol=1e-6, max_iters=1000, precision=AIM_FP64, check_every=1,

@@ -84,6 +84,9 @@ EXPORTS = {
                                      ctypes.c_int32, ctypes.c_void_p]),
     "aim_far_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, _f64p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "aim_far_field_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                             _f64p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                             ctypes.c_void_p]),
     "aim_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AimInfo)]),
     "aim_get_near": (ctypes.c_int, [ctypes.c_void_p, _i32p, _i32p, _i32p, _f64p, _i32p]),
     "aim_footprint_bytes": (ctypes.c_size_t, [ctypes.POINTER(AimSurface), ctypes.POINTER(AimArray),

@@ -614,6 +614,7 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
     op->nf = op->mem.alloc<cplx<double>>(size_t(op->ne) * st.grp_row.size() * a.max_rhs);
     op->grid = op->mem.alloc<cplx<double>>(size_t(a.max_rhs) * 4 * st.nx * st.ny * st.nz);
     op->S = op->mem.alloc<cplx<double>>(size_t(a.max_rhs) * 4 * st.nx * op->Ly * st.nz);
+    ff_prepare(op);
   } catch (const std::bad_alloc&) {
     delete op;
     set_error("device or host allocation failed");

@@ -15,6 +15,7 @@
 // writes one partial per tile of RWG functions; a last kernel sums the partials in a
 // fixed order, projects out the radial part and forms 10 log10(4 pi |E|^2).
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -174,6 +175,43 @@ __global__ void k_ff_finish(const cplx<double>* __restrict__ part, const double*
 // bytes of the direction block at the head of the workspace (256-byte aligned tail)
 inline size_t ff_dir_bytes(int ndir) { return (size_t(ndir) * 3 * sizeof(double) + 255) / 256 * 256; }
 
+// Workspace bytes of one far-field call: directions, phase tables and per-tile partials.
+inline size_t ff_need_bytes(int ndir, int px, int py, int ntiles, int nrhs) {
+  return ff_dir_bytes(ndir) + size_t(ndir) * (px + py) * sizeof(cplx<double>) +
+         size_t(ntiles) * nrhs * ndir * 3 * sizeof(cplx<double>);
+}
+
+// Workspace of the allocation-free entry point aim_far_field_noalloc: one copy per GPU,
+// kept until the process ends.  Host code never uses this name as an address: the
+// device address of each GPU's copy is looked up once per device (ff_scratch_ptr).
+constexpr size_t kFfScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kFfScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current), resolved on first use.
+hipError_t ff_scratch_ptr(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+// The address resolved for `device` by ff_scratch_ptr, or NULL (no HIP call).
+void* ff_scratch_lookup(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
 }  // namespace
 }  // namespace aimm
 
@@ -188,8 +226,40 @@ using namespace aimm;
     }                                                                                    \
   } while (0)
 
-extern "C" int aim_far_field(aim_op* op, const void* x, int32_t nrhs, int32_t ndir, const double* rhat, void* E,
-                             void* rcs_db, int32_t system, void* stream) {
+namespace aimm {
+
+// Set-up of the far field at op build time, on the op's device (current): the
+// quadrature table of the RWG radiation integrals, and the device address of this
+// GPU's scratch array.  Throws std::bad_alloc or std::runtime_error.
+void ff_prepare(aim_op* op) {
+  if (!op->ff_quad) {
+    SurfaceIn sf;
+    sf.n_vert = int(op->vert.size() / 3);
+    sf.n_tri = int(op->tri.size() / 3);
+    sf.n_rwg = int(op->rwg.size() / 4);
+    sf.vert = op->vert.data();
+    sf.tri = op->tri.data();
+    sf.rwg = op->rwg.data();
+    std::vector<double> q;
+    far_quadrature(sf, q);
+    op->ff_quad = op->mem.alloc<double>(q.size());
+    if (hipMemcpy(op->ff_quad, q.data(), q.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+      throw std::runtime_error("far field: hipMemcpy of the quadrature table failed");
+  }
+  void* p = nullptr;
+  const hipError_t e = ff_scratch_ptr(op->device, &p);
+  if (e != hipSuccess)
+    throw std::runtime_error(std::string("far field: hipGetSymbolAddress(scratch) failed: ") +
+                             hipGetErrorString(e));
+}
+
+}  // namespace aimm
+
+namespace {
+
+// Argument checks shared by both entry points (nothing is modified on failure).
+int ff_check(aim_op* op, const void* x, int32_t nrhs, int32_t ndir, const double* rhat, void* E,
+             int32_t system) {
   if (!op || !x || !rhat || !E || ndir < 1) {
     set_error("far field: op, x, rhat and E must not be NULL and ndir >= 1");
     return AIM_EINVAL;
@@ -207,47 +277,20 @@ extern "C" int aim_far_field(aim_op* op, const void* x, int32_t nrhs, int32_t nd
     set_error("far field: system must be AIM_FULL or AIM_G_ONLY");
     return AIM_EINVAL;
   }
-  if (!op->device_ready || (system == AIM_FULL && !op->m_set)) {
+  if (!op->device_ready || (system == AIM_FULL && !op->m_set) || !op->ff_quad) {
     set_error("far field: device data and macromodels must be set");
     return AIM_ESTATE;
   }
-  hipStream_t s = static_cast<hipStream_t>(stream);
+  return AIM_OK;
+}
+
+// The far-field launches on the workspace ws (at least ff_need_bytes of the call).
+int ff_run(aim_op* op, const void* x, int32_t nrhs, int32_t ndir, const double* rhat, void* E, void* rcs_db,
+           int32_t system, hipStream_t s, unsigned char* ws) {
   const int N = op->N, ne = op->ne, px = op->arr.px, py = op->arr.py;
   const int ntiles = (N + kFfN - 1) / kFfN;
-  try {
-    if (!op->ff_quad) {
-      SurfaceIn sf;
-      sf.n_vert = int(op->vert.size() / 3);
-      sf.n_tri = int(op->tri.size() / 3);
-      sf.n_rwg = int(op->rwg.size() / 4);
-      sf.vert = op->vert.data();
-      sf.tri = op->tri.data();
-      sf.rwg = op->rwg.data();
-      std::vector<double> q;
-      far_quadrature(sf, q);
-      op->ff_quad = op->mem.alloc<double>(q.size());
-      FF_HIP(hipMemcpy(op->ff_quad, q.data(), q.size() * sizeof(double), hipMemcpyHostToDevice));
-    }
-    // workspace: directions, phase tables and per-tile partials, grown on demand
-    const size_t need = ff_dir_bytes(ndir) + size_t(ndir) * (px + py) * sizeof(cplx<double>) +
-                        size_t(ntiles) * op->R_max * ndir * 3 * sizeof(cplx<double>);
-    if (need > op->ff_bytes) {
-      if (op->ff_ws) {
-        FF_HIP(hipStreamSynchronize(s));
-        op->mem.release(op->ff_ws, op->ff_bytes);
-        op->ff_ws = nullptr;
-        op->ff_bytes = 0;
-      }
-      op->ff_ws = op->mem.alloc<unsigned char>(need);
-      op->ff_bytes = need;
-    }
-  } catch (const std::bad_alloc&) {
-    set_error("far field: device allocation failed");
-    return AIM_ENOMEM;
-  }
-  unsigned char* w = static_cast<unsigned char*>(op->ff_ws);
-  double* rd = reinterpret_cast<double*>(w);
-  cplx<double>* X = reinterpret_cast<cplx<double>*>(w + ff_dir_bytes(ndir));
+  double* rd = reinterpret_cast<double*>(ws);
+  cplx<double>* X = reinterpret_cast<cplx<double>*>(ws + ff_dir_bytes(ndir));
   cplx<double>* Y = X + size_t(ndir) * px;
   cplx<double>* part = Y + size_t(ndir) * py;
   FF_HIP(hipMemcpyAsync(rd, rhat, size_t(ndir) * 3 * sizeof(double), hipMemcpyHostToDevice, s));
@@ -278,9 +321,58 @@ extern "C" int aim_far_field(aim_op* op, const void* x, int32_t nrhs, int32_t nd
   a.part = part;
   hipLaunchKernelGGL(k_ff_gemm, dim3((ndir + kFfD - 1) / kFfD, ntiles, nrhs), dim3(256), 0, s, uT, a);
   FF_HIP(hipGetLastError());
+  const double keta = (system == AIM_FULL ? -1.0 : 1.0) * op->arr.k * op->arr.eta;
   hipLaunchKernelGGL(k_ff_finish, dim3((nrhs * ndir + 255) / 256), dim3(256), 0, s, part, rd,
-                     static_cast<cplx<double>*>(E), static_cast<double*>(rcs_db), ndir, nrhs, ntiles,
-                     (system == AIM_FULL ? -1.0 : 1.0) * op->arr.k * op->arr.eta);
+                     static_cast<cplx<double>*>(E), static_cast<double*>(rcs_db), ndir, nrhs, ntiles, keta);
   FF_HIP(hipGetLastError());
   return AIM_OK;
+}
+
+}  // namespace
+
+extern "C" int aim_far_field(aim_op* op, const void* x, int32_t nrhs, int32_t ndir, const double* rhat, void* E,
+                             void* rcs_db, int32_t system, void* stream) {
+  const int rc = ff_check(op, x, nrhs, ndir, rhat, E, system);
+  if (rc != AIM_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ntiles = (op->N + kFfN - 1) / kFfN;
+  try {
+    // workspace: directions, phase tables and per-tile partials, grown on demand
+    const size_t need = ff_need_bytes(ndir, op->arr.px, op->arr.py, ntiles, op->R_max);
+    if (need > op->ff_bytes) {
+      if (op->ff_ws) {
+        FF_HIP(hipStreamSynchronize(s));
+        op->mem.release(op->ff_ws, op->ff_bytes);
+        op->ff_ws = nullptr;
+        op->ff_bytes = 0;
+      }
+      op->ff_ws = op->mem.alloc<unsigned char>(need);
+      op->ff_bytes = need;
+    }
+  } catch (const std::bad_alloc&) {
+    set_error("far field: device allocation failed");
+    return AIM_ENOMEM;
+  }
+  return ff_run(op, x, nrhs, ndir, rhat, E, rcs_db, system, s, static_cast<unsigned char*>(op->ff_ws));
+}
+
+extern "C" int aim_far_field_noalloc(aim_op* op, const void* x, int32_t nrhs, int32_t ndir, const double* rhat,
+                                     void* E, void* rcs_db, int32_t system, void* stream) {
+  const int rc = ff_check(op, x, nrhs, ndir, rhat, E, system);
+  if (rc != AIM_OK) return rc;
+  const int ntiles = (op->N + kFfN - 1) / kFfN;
+  const size_t need = ff_need_bytes(ndir, op->arr.px, op->arr.py, ntiles, nrhs);
+  if (need > kFfScratchBytes) {
+    set_error("far field (no allocation): the call needs " + std::to_string(need) +
+              " bytes of workspace, more than the " + std::to_string(kFfScratchBytes) +
+              "-byte scratch array; use fewer directions or right-hand sides per call");
+    return AIM_EINVAL;
+  }
+  void* ws = ff_scratch_lookup(op->device);  // resolved when the op was built
+  if (!ws) {
+    set_error("far field (no allocation): scratch address of the op's device is not set");
+    return AIM_ESTATE;
+  }
+  return ff_run(op, x, nrhs, ndir, rhat, E, rcs_db, system, static_cast<hipStream_t>(stream),
+                static_cast<unsigned char*>(ws));
 }

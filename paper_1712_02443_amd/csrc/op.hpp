@@ -90,6 +90,8 @@ struct KrylovWork {
 };
 
 void release_krylov(aim_op* op);
+// far-field set-up at op build time (quadrature table, scratch address of the device)
+void ff_prepare(aim_op* op);
 // grouped-product arguments of the op's macromodel layout for R right-hand sides
 GemmArgs gemm_args_of(aim_op* op, int R);
 
