@@ -16,7 +16,11 @@ What it computes, each function citing the passage of the paper it follows:
     with T A^-1 B given as the per-type block M_t (section III);
   * GMRES(m) on the final system (section V, eq. finalsystem), optionally right
     preconditioned with the per-kind block-Jacobi inverse of the diagonal blocks;
-  * the plane-wave excitation vector (section IV eq. V1) and the radiated far field;
+  * the macromodel of one element (section II, section III): Buffa-Christiansen dual
+    functions on the equivalent box, the L- and K-type Galerkin blocks between the
+    scatterer and the box, D (section IV), and A, B, T, R = A^-1 B and M = T A^-1 B;
+  * the plane-wave excitation vector (section IV eq. V1), the radiated far field and
+    the field at finite points;
   * the Mie series of a perfectly conducting sphere, an analytic reference for the
     EFIE, excitation and far field together.
 

@@ -66,3 +66,28 @@ def radiated_field(geo: RwgGeom, centers: np.ndarray, J: np.ndarray, rhat: np.nd
 def rcs_db(E: np.ndarray) -> np.ndarray:
     """Bistatic RCS 10 log10(4 pi |E_far|^2 / |E0|^2) in dB relative to lambda^2 (E0 = 1)."""
     return 10.0 * np.log10(4.0 * np.pi * np.maximum((np.abs(E) ** 2).sum(-1), 1e-300))
+
+
+def radiated_near_field(geo: RwgGeom, centers: np.ndarray, J: np.ndarray, points: np.ndarray,
+                        k: float, eta: float) -> np.ndarray:
+    """E(r) of surface currents J (element-major) at points (P, 3) away from the surfaces:
+    E = -j k eta int J G dS' - j (eta / k) grad int (div' J) G dS'  (G = exp(-j k R) / (4 pi R)),
+    the 7-point rule on every source triangle (points must be well separated from them)."""
+    Jm = J.reshape(centers.shape[0], geo.n_rwg)
+    out = np.zeros((points.shape[0], 3), dtype=np.complex128)
+    for sgn, tidx, free in ((1.0, geo.tp, geo.pp), (-1.0, geo.tm, geo.pm)):
+        tv = geo.tri_vert[tidx]
+        A = geo.tri_area[tidx]
+        rq = np.einsum("qi,nik->nqk", _BARY, tv)
+        lam = sgn * (geo.length / (2.0 * A))[:, None, None] * (rq - free[:, None, :])  # (n, 7, 3)
+        div = sgn * geo.length / A                                                     # (n,)
+        for m in range(centers.shape[0]):
+            src = rq + centers[m]
+            d = points[:, None, None, :] - src[None]                                  # (P, n, 7, 3)
+            R = np.sqrt((d * d).sum(-1))
+            G = np.exp(-1j * k * R) / (4.0 * np.pi * R)
+            dG = -(1.0 + 1j * k * R) * G / R                                          # dG/dR
+            w = _W[None, None, :] * A[None, :, None] * Jm[m][None, :, None]           # (P, n, 7)
+            out += -1j * k * eta * np.einsum("pnq,nqk->pk", w * G, lam)
+            out += -1j * (eta / k) * np.einsum("pnq,n,pnqk->pk", w * dG / R, div, d)
+    return out

@@ -10,15 +10,14 @@ What this module draws, all from numpy's PCG64 with one integer seed per
 workload and one independent stream per kind of draw:
   * the element type at every lattice site (stream 0);
   * incidence angles and polarisations (stream 1);
-  * the per-type macromodel block M_t = T_t A_t^-1 B_t (section II-F, eq. Tm1 and
-    eq. JABE): a dense complex N x N matrix.  Computing it needs the full
-    element-level surface integral equations (section II), which sit outside the
-    solve-time path; the blocks here are seeded stand-ins with a fixed spectral
-    scale (stream 2);
-  * the per-type sparse matrix D_t (section IV, the RWG / dual-RWG Gram matrix):
-    its sparsity follows the overlap of an RWG function with the dual functions
-    anchored on the vertices of neighbouring edges, its values are seeded and
-    diagonally dominant, as the paper states D is (stream 3);
+  * the PEC scatterer of every element kind (geometry only): square plates and the
+    Jerusalem cross, from which the physical per-kind blocks M_t = T_t A_t^-1 B_t and
+    D_t (section II, section IV) are computed by the library (and by the oracle in
+    tests);
+  * seeded stand-ins for M_t and D_t, kept for kernel tests whose results do not
+    depend on the operator's physics: dense complex Gaussian blocks with a fixed
+    spectral scale (stream 2) and a sparse D with the pattern of the RWG / dual-RWG
+    overlap and diagonally dominant seeded values (stream 3);
   * test vectors for matrix-vector products (stream 4).
 Nothing here evaluates an integral, a basis function or an operator product.
 """
@@ -29,7 +28,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .mesh import SurfaceMesh, cube_surface, jerusalem_cross
+from .mesh import SurfaceMesh, cube_surface, jerusalem_cross, square_plate
 
 ETA0 = 376.730313668
 K0 = 2.0 * math.pi
@@ -64,6 +63,7 @@ class Workload:
     pitch_cells: int = 6
     seed: int = 0
     macro_scale: float = 1.0e-3
+    element_specs: tuple = ()
     _mesh: SurfaceMesh | None = field(default=None, repr=False)
 
     @property
@@ -101,6 +101,11 @@ class Workload:
     def macromodels(self) -> np.ndarray:
         return synthetic_macromodels(self.n_types, self.n_rwg, self.seed, self.macro_scale)
 
+    def element_meshes(self) -> list[SurfaceMesh]:
+        """The PEC scatterer surface of every element kind, in the element's local frame
+        (geometry only): the plates and Jerusalem crosses that the equivalent boxes enclose."""
+        return [element_mesh(spec) for spec in self.element_specs]
+
     def d_matrix(self):
         return synthetic_d_matrix(self.surface, self.seed)
 
@@ -110,6 +115,16 @@ class Workload:
         n = self.nrhs if nrhs is None else nrhs
         z = r.standard_normal((n, self.n_unknowns)) + 1j * r.standard_normal((n, self.n_unknowns))
         return z.astype(dtype)
+
+
+def element_mesh(spec: tuple) -> SurfaceMesh:
+    """("plate", side, n): square plate of that side on n x n squares;
+    ("jc", cell): the Jerusalem cross (arms 0.4, width 0.04, caps 0.2 x 0.02) on cell-sized squares."""
+    if spec[0] == "plate":
+        return square_plate(float(spec[1]), int(spec[2]))
+    if spec[0] == "jc":
+        return jerusalem_cross(cell=float(spec[1]))
+    raise ValueError(f"unknown element {spec!r}")
 
 
 def synthetic_macromodels(n_types: int, n: int, seed: int, scale: float) -> np.ndarray:
@@ -172,7 +187,8 @@ def make_workload(index: int, seed: int = 0, px: int | None = None, py: int | No
         Q = P if py is None else py
         types = np.zeros(P * Q, dtype=np.int32)
         return Workload("plates-2x2-fp64", P, Q, 0.5, 4, 1, types,
-                        np.array([0.0]), np.array([0.0]), np.array([0], dtype=np.int32), seed=seed)
+                        np.array([0.0]), np.array([0.0]), np.array([0], dtype=np.int32), seed=seed,
+                        element_specs=(("plate", 0.4, 8),))
     if index == 1:
         P = 32 if px is None else px
         Q = P if py is None else py
@@ -180,7 +196,7 @@ def make_workload(index: int, seed: int = 0, px: int | None = None, py: int | No
         n = 1 if nrhs is None else nrhs
         return Workload("jc-32x32-mixed", P, Q, 0.55, 6, 1, types,
                         np.full(n, math.radians(30.0)), np.full(n, math.radians(45.0)),
-                        np.zeros(n, dtype=np.int32), seed=seed)
+                        np.zeros(n, dtype=np.int32), seed=seed, element_specs=(("jc", 0.01),))
     if index == 2:
         P = 16 if px is None else px
         Q = P if py is None else py
@@ -188,7 +204,8 @@ def make_workload(index: int, seed: int = 0, px: int | None = None, py: int | No
         n = 64 if nrhs is None else nrhs
         th, ph = _angles_uniform(rng(seed, STREAM_INC), n)
         pol = np.array([0 if i % 2 == 1 else 1 for i in range(n)], dtype=np.int32)
-        return Workload("plates-16x16-64rhs", P, Q, 0.5, 4, 3, types, th, ph, pol, seed=seed)
+        return Workload("plates-16x16-64rhs", P, Q, 0.5, 4, 3, types, th, ph, pol, seed=seed,
+                        element_specs=(("plate", 0.30, 8), ("plate", 0.35, 8), ("plate", 0.40, 8)))
     if index == 4:
         P = 64 if px is None else px
         Q = P if py is None else py
@@ -198,7 +215,7 @@ def make_workload(index: int, seed: int = 0, px: int | None = None, py: int | No
         th = np.array([math.radians((0.0, 20.0, 40.0, 60.0)[(i // 2) % 4]) for i in range(n)])
         pol = np.array([i % 2 for i in range(n)], dtype=np.int32)
         return Workload("jc-64x64-8rhs", P, Q, 0.55, 6, 2, types, th, np.zeros(n), pol,
-                        restart=80, seed=seed)
+                        restart=80, seed=seed, element_specs=(("jc", 0.01), ("plate", 0.3, 8)))
     raise ValueError(f"no workload {index} (workload 3 is the request trace, see serving_trace)")
 
 
