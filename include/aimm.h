@@ -266,6 +266,39 @@ int aim_far_field(aim_op* op, const void* x, int32_t nrhs, int32_t ndir, const d
 int aim_far_field_noalloc(aim_op* op, const void* x, int32_t nrhs, int32_t ndir, const double* rhat, void* E,
                           void* rcs_db, int32_t system, void* stream);
 
+/* Macromodel generation (section II, section III) in the library, on the device, for
+ * every element kind: scatterers[t] is the PEC surface of kind t (element-local
+ * coordinates, inside the op's equivalent surface; RWG table as for aim_surface).  With
+ * the op's surface as the equivalent surface S^ (n its inward normal) the library fills
+ * the Galerkin blocks of eq. Gm_EJ_1 - Gm_EJ_3 and eq. G1 - G3 (L-type with the kernel's
+ * static part in closed form; K-type with the Buffa-Christiansen dual functions on the
+ * barycentric refinement of S^, principal value plus D / 2 on S^ itself), D of section
+ * IV, then [T | Y] = G^(E^,H^)^-1 [G^(E^,J) | G^(E^,E^)], [A | B] = [G^(E,J) | G^(E,E^)] -
+ * G^(E,H^) [T | Y] (eq. JM), R = A^-1 B and M = T R (eq. JABE, eq. Tm1) in FP64 by
+ * Gauss-Jordan elimination and GEMMs on the matrix cores.  It then sets M (as
+ * aim_set_macromodels) and D (as aim_set_dmatrix) on the op and keeps each kind's R on
+ * the device for aim_recover_currents.  AIM_ESTATE if D is already set or the op is
+ * host-only; AIM_EINVAL for a bad or open mesh or a singular block (an equivalent
+ * surface at an interior resonance).  Synchronises the stream; allocates (and frees)
+ * temporary device memory of about 144 n_tri^2 bytes for the largest mesh. */
+int aim_build_macromodels(aim_op* op, const aim_surface* scatterers, void* stream);
+
+/* Host copies of kind `kind`'s generated blocks: M complex128 [N][N], R = A^-1 B complex128
+ * [N_t][N] (N_t = RWG functions of the kind's scatterer), D real [N][N], all column-major;
+ * any output may be NULL.  AIM_ESTATE unless aim_build_macromodels succeeded on the op. */
+int aim_get_macromodel(const aim_op* op, int32_t kind, double* M, double* R, double* D);
+
+/* Scatterer unknowns: of kind `kind` (>= 0), or of the whole array (kind = -1, the sum
+ * of the elements' N_t); -1 before aim_build_macromodels. */
+int64_t aim_scatterer_unknowns(const aim_op* op, int32_t kind);
+
+/* Current recovery on the original scatterers, J_m = -R_t(m) E^_m for every element m
+ * (eq. JABE; the paper's inexpensive step after the solve), FP64, as grouped GEMMs on
+ * the matrix cores.  x: device complex128 [nrhs][n_elem][N] (solutions of gmres_solve);
+ * J: device complex128 [nrhs][aim_scatterer_unknowns(op, -1)], element-major with
+ * element m's N_t(m) values after those of elements 0..m-1.  Synchronises the stream. */
+int aim_recover_currents(aim_op* op, const void* x, void* J, int32_t nrhs, void* stream);
+
 /* Sizes of the op (host only, no device work). */
 int aim_get_info(const aim_op* op, aim_info* info);
 

@@ -22,7 +22,7 @@ from .geometry import rwg_geometry
 
 class OracleOperator:
     def __init__(self, wl: Workload, near_mode: str = "offset", g0: complex = 0.0, pad=None,
-                 M: np.ndarray | None = None, near: bool = True):
+                 M: np.ndarray | None = None, near: bool = True, D=None):
         self.wl = wl
         mesh = wl.surface
         self.geo = rwg_geometry(mesh.vert, mesh.tri, mesh.rwg)
@@ -33,7 +33,8 @@ class OracleOperator:
         self.Gs = aim.green_samples(self.grid.shape, wl.h, wl.k, g0)
         self.pad = pad
         self.M = wl.macromodels() if M is None else M
-        r, c, v = wl.d_matrix()
+        # D as (rows, cols, values); the workload's seeded stand-in unless given
+        r, c, v = wl.d_matrix() if D is None else D
         self.D = sp.csr_matrix((v, (r, c)), shape=(self.nb, self.nb))
         self.near_mode = near_mode
         # near=False skips the (slow) pre-corrected near field for uses of the grid part

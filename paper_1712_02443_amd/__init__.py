@@ -90,6 +90,44 @@ class AimOperator:
         check(self.lib.aim_set_dmatrix(self._op, r.shape[0], r.ctypes.data_as(_lib._i32p),
                                        c.ctypes.data_as(_lib._i32p), v.view(np.float64).ctypes.data_as(_lib._f64p)))
 
+    def build_macromodels(self, meshes, stream=None):
+        """Generate every kind's M_t, R_t = A_t^-1 B_t and D on the device from the PEC
+        scatterer meshes (one per kind: objects with vert, tri, rwg), and set M and D."""
+        if len(meshes) != self.info()["n_types"]:
+            raise ValueError("one scatterer mesh per element kind is needed")
+        keep = []
+        surfs = (_lib.AimSurface * len(meshes))()
+        for i, m in enumerate(meshes):
+            v = np.ascontiguousarray(m.vert, dtype=np.float64)
+            t = np.ascontiguousarray(m.tri, dtype=np.int32)
+            r = np.ascontiguousarray(m.rwg, dtype=np.int32)
+            keep += [v, t, r]
+            surfs[i] = _lib.AimSurface(v.shape[0], t.shape[0], r.shape[0], v.ctypes.data_as(_lib._f64p),
+                                       t.ctypes.data_as(_lib._i32p), r.ctypes.data_as(_lib._i32p))
+        check(self.lib.aim_build_macromodels(self._op, surfs, _stream(self._torch, stream)))
+        self._n_scat = [int(self.lib.aim_scatterer_unknowns(self._op, t)) for t in range(len(meshes))]
+
+    def macromodel(self, kind: int):
+        """Generated blocks of one kind: M (N, N), R (N_t, N) complex128 and D (N, N) real."""
+        N = self.n_rwg
+        Nt = self._n_scat[kind]
+        M = np.empty((N, N), np.complex128)
+        R = np.empty((N, Nt), np.complex128)
+        D = np.empty((N, N), np.float64)
+        check(self.lib.aim_get_macromodel(self._op, int(kind), M.view(np.float64).ctypes.data_as(_lib._f64p),
+                                          R.view(np.float64).ctypes.data_as(_lib._f64p),
+                                          D.ctypes.data_as(_lib._f64p)))
+        # column-major storage read back as row-major is the transpose
+        return M.T.copy(), R.T.copy(), D.T.copy()
+
+    def recover_currents(self, x, stream=None):
+        """J = -R_t E^ on every element's scatterer (device complex128 (nrhs, total scatterer unknowns))."""
+        R = self._check_vec(x, AIM_FP64)
+        ntot = int(self.lib.aim_scatterer_unknowns(self._op, -1))
+        J = self._torch.empty((R, ntot), dtype=self._torch.complex128, device=x.device)
+        check(self.lib.aim_recover_currents(self._op, _dev_ptr(x), _dev_ptr(J), R, _stream(self._torch, stream)))
+        return J
+
     def build_preconditioner(self):
         """Per-kind block-Jacobi blocks P_t = (D - G_self M_t)^-1 (host FP64, then the device)."""
         check(self.lib.aim_build_preconditioner(self._op))

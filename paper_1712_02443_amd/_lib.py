@@ -87,6 +87,11 @@ EXPORTS = {
     "aim_far_field_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                              _f64p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                              ctypes.c_void_p]),
+    "aim_build_macromodels": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AimSurface), ctypes.c_void_p]),
+    "aim_get_macromodel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, _f64p, _f64p]),
+    "aim_scatterer_unknowns": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int32]),
+    "aim_recover_currents": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_void_p]),
     "aim_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AimInfo)]),
     "aim_get_near": (ctypes.c_int, [ctypes.c_void_p, _i32p, _i32p, _i32p, _f64p, _i32p]),
     "aim_footprint_bytes": (ctypes.c_size_t, [ctypes.POINTER(AimSurface), ctypes.POINTER(AimArray),

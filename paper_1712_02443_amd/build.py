@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaimm.so")
-SOURCES = ["setup.cpp", "precond.cpp", "aim_kernels.hip", "api.hip", "gmres.hip", "farfield.hip"]
+SOURCES = ["setup.cpp", "precond.cpp", "aim_kernels.hip", "api.hip", "gmres.hip", "farfield.hip", "macromodel.hip"]
 
 # Packed FP32 instructions are disabled for every device compile (hipcc's host pass
 # warns that it does not know the feature; that is harmless).

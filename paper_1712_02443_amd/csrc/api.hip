@@ -1065,6 +1065,7 @@ void aim_destroy(aim_op* op) {
     if (op->ev_fork) (void)hipEventDestroy(op->ev_fork);
     if (op->ev_join) (void)hipEventDestroy(op->ev_join);
   }
+  aimm_release_macro_store(op);
   delete op;
 }
 

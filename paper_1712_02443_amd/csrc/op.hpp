@@ -97,6 +97,9 @@ GemmArgs gemm_args_of(aim_op* op, int R);
 
 }  // namespace aimm
 
+// frees the generated macromodel data of an op (R blocks, host copies); called by aim_destroy
+void aimm_release_macro_store(const aim_op* op);
+
 struct aim_op {
   aimm::Setup st;
   aimm::ArrayIn arr{};
