@@ -113,8 +113,9 @@ typedef struct {
  * interpolation weights, FFT plan and Green's-function spectrum (on the device),
  * and the pre-corrected near field (exact entries of eq. Gouter1 on near pairs minus
  * their grid approximation).  Allocates device memory for max_rhs right-hand sides.
- * Uses the current HIP device.  *out is set only on success. */
-int aim_build_grid(const aim_surface* surface, const aim_array* array, aim_op** out);
+ * Uses the current HIP device; uploads and the spectrum kernels run on `stream`, which
+ * is synchronised before the call returns.  *out is set only on success. */
+int aim_build_grid(const aim_surface* surface, const aim_array* array, void* stream, aim_op** out);
 
 /* The host part of aim_build_grid alone: stencils, weights and the pre-corrected
  * near field, with no device call.  The op serves aim_get_info, aim_get_near and

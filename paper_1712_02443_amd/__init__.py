@@ -40,7 +40,7 @@ class AimOperator:
     """One array problem on the current GPU (see include/aimm.h for the conventions)."""
 
     def __init__(self, vert, tri, rwg, *, k, eta, h, r_near, order, px, py, pitch_cells, elem_type, n_types,
-                 max_rhs=1, host_only=False):
+                 max_rhs=1, host_only=False, stream=None):
         self.lib = load()
         self._op = None
         self._st = _lib.Structs(vert, tri, rwg, k, eta, h, r_near, order, px, py, pitch_cells, elem_type,
@@ -49,8 +49,12 @@ class AimOperator:
             import torch
             self._torch = torch
         h_op = ctypes.c_void_p()
-        build = self.lib.aim_build_host if host_only else self.lib.aim_build_grid
-        check(build(ctypes.byref(self._st.surface), ctypes.byref(self._st.array), ctypes.byref(h_op)))
+        if host_only:
+            check(self.lib.aim_build_host(ctypes.byref(self._st.surface), ctypes.byref(self._st.array),
+                                          ctypes.byref(h_op)))
+        else:
+            check(self.lib.aim_build_grid(ctypes.byref(self._st.surface), ctypes.byref(self._st.array),
+                                          _stream(self._torch, stream), ctypes.byref(h_op)))
         self._op = h_op
         self.max_rhs = int(max_rhs)
         inf = self.info()

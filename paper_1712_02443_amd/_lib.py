@@ -58,7 +58,7 @@ class GmresStat(ctypes.Structure):
 _LIB = None
 
 EXPORTS = {
-    "aim_build_grid": (ctypes.c_int, [ctypes.POINTER(AimSurface), ctypes.POINTER(AimArray),
+    "aim_build_grid": (ctypes.c_int, [ctypes.POINTER(AimSurface), ctypes.POINTER(AimArray), ctypes.c_void_p,
                                       ctypes.POINTER(ctypes.c_void_p)]),
     "aim_build_host": (ctypes.c_int, [ctypes.POINTER(AimSurface), ctypes.POINTER(AimArray),
                                       ctypes.POINTER(ctypes.c_void_p)]),

@@ -70,10 +70,13 @@ static void twiddles(int L, std::vector<cplx<T>>& out) {
   }
 }
 
+// Copy of host data to new device memory, on the stream the op is built on (the copy has
+// completed on return).
 template <typename T>
 static T* upload(aim_op* op, const T* host, size_t n) {
   T* d = op->mem.alloc<T>(n);
-  if (n && hipMemcpy(d, host, n * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+  if (n && (hipMemcpyAsync(d, host, n * sizeof(T), hipMemcpyHostToDevice, op->build_stream) != hipSuccess ||
+            hipStreamSynchronize(op->build_stream) != hipSuccess))
     throw std::runtime_error("hipMemcpy upload failed");
   return d;
 }
@@ -445,7 +448,8 @@ extern "C" {
 
 const char* aim_last_error(void) { return aimm::g_err.c_str(); }
 
-static int build_op(const aim_surface* surface, const aim_array* array, aim_op** out, bool device) {
+static int build_op(const aim_surface* surface, const aim_array* array, aim_op** out, bool device,
+                    hipStream_t stream) {
   if (!surface || !array || !out) {
     set_error("surface, array and out must not be NULL");
     return AIM_EINVAL;
@@ -474,6 +478,7 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
     validate(s, a);
     if (a.n_types > kMaxTypes) throw std::invalid_argument("n_types exceeds 16");
     op = new aim_op();
+    op->build_stream = stream;
     op->vert.assign(s.vert, s.vert + 3 * s.n_vert);
     op->tri.assign(s.tri, s.tri + 3 * s.n_tri);
     op->rwg.assign(s.rwg, s.rwg + 4 * s.n_rwg);
@@ -599,10 +604,12 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
       int* pxd = upload(op, px_.data(), px_.size());
       int* pyd = upload(op, py_.data(), py_.size());
       hipError_t e = launch_spectrum(raw, op->Lx, op->Ly, st.nz, a.k, a.h, op->Px, op->Py, op->p64.tw_x,
-                                     op->p64.tw_y, 1, nullptr);
-      if (e == hipSuccess) e = launch_extract<double>(raw, op->p64.gt, op->Lx, op->Ly, st.nz, pxd, pyd, nullptr);
-      if (e == hipSuccess) e = launch_extract<float>(raw, op->p32.gt, op->Lx, op->Ly, st.nz, pxd, pyd, nullptr);
-      if (e == hipSuccess) e = hipDeviceSynchronize();
+                                     op->p64.tw_y, 1, op->build_stream);
+      if (e == hipSuccess)
+        e = launch_extract<double>(raw, op->p64.gt, op->Lx, op->Ly, st.nz, pxd, pyd, op->build_stream);
+      if (e == hipSuccess)
+        e = launch_extract<float>(raw, op->p32.gt, op->Lx, op->Ly, st.nz, pxd, pyd, op->build_stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(op->build_stream);
       if (e != hipSuccess) throw std::runtime_error(std::string("spectrum build: ") + hipGetErrorString(e));
       op->mem.release(raw, sizeof(cplx<double>) * size_t(op->Lx) * op->Ly * st.nz);
       op->mem.release(pxd, sizeof(int) * px_.size());
@@ -615,6 +622,9 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
     op->grid = op->mem.alloc<cplx<double>>(size_t(a.max_rhs) * 4 * st.nx * st.ny * st.nz);
     op->S = op->mem.alloc<cplx<double>>(size_t(a.max_rhs) * 4 * st.nx * op->Ly * st.nz);
     ff_prepare(op);
+    // later uploads (operator data, preconditioner) run on the null stream: the build
+    // stream may not outlive this call
+    op->build_stream = nullptr;
   } catch (const std::bad_alloc&) {
     delete op;
     set_error("device or host allocation failed");
@@ -632,12 +642,12 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
   return AIM_OK;
 }
 
-int aim_build_grid(const aim_surface* surface, const aim_array* array, aim_op** out) {
-  return build_op(surface, array, out, true);
+int aim_build_grid(const aim_surface* surface, const aim_array* array, void* stream, aim_op** out) {
+  return build_op(surface, array, out, true, static_cast<hipStream_t>(stream));
 }
 
 int aim_build_host(const aim_surface* surface, const aim_array* array, aim_op** out) {
-  return build_op(surface, array, out, false);
+  return build_op(surface, array, out, false, nullptr);
 }
 
 

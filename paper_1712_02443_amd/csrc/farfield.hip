@@ -243,7 +243,9 @@ void ff_prepare(aim_op* op) {
     std::vector<double> q;
     far_quadrature(sf, q);
     op->ff_quad = op->mem.alloc<double>(q.size());
-    if (hipMemcpy(op->ff_quad, q.data(), q.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpyAsync(op->ff_quad, q.data(), q.size() * sizeof(double), hipMemcpyHostToDevice,
+                       op->build_stream) != hipSuccess ||
+        hipStreamSynchronize(op->build_stream) != hipSuccess)
       throw std::runtime_error("far field: hipMemcpy of the quadrature table failed");
   }
   void* p = nullptr;

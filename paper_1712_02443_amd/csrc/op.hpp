@@ -107,6 +107,7 @@ struct aim_op {
   std::vector<double> vert;
   std::vector<int32_t> tri, rwg;
   int device = 0;
+  hipStream_t build_stream = nullptr;  // stream of aim_build_grid's uploads and kernels (during the call)
   int ne = 0, N = 0, R_max = 0, n_types = 0;
   int Lx = 0, Ly = 0;
   aimm::FftPlan Px{}, Py{};
