@@ -117,6 +117,14 @@ typedef struct {
  * is synchronised before the call returns.  *out is set only on success. */
 int aim_build_grid(const aim_surface* surface, const aim_array* array, void* stream, aim_op** out);
 
+/* Change the kind of every element (host [py*px], values in [0, n_types)) of a built op,
+ * keeping its grid, Green's-function spectrum, near field, macromodels, D and
+ * preconditioner blocks, which do not depend on where each kind sits (section III: the
+ * blocks are per distinct element).  For serving many arrays of one size with one op.
+ * The op must have no work in flight on any stream; the copy runs on `stream`, which is
+ * synchronised before the call returns. */
+int aim_set_elem_type(aim_op* op, const int32_t* elem_type, void* stream);
+
 /* The host part of aim_build_grid alone: stencils, weights and the pre-corrected
  * near field, with no device call.  The op serves aim_get_info, aim_get_near and
  * the host parts of aim_set_macromodels, aim_set_dmatrix, aim_build_preconditioner

@@ -63,6 +63,7 @@ EXPORTS = {
     "aim_build_host": (ctypes.c_int, [ctypes.POINTER(AimSurface), ctypes.POINTER(AimArray),
                                       ctypes.POINTER(ctypes.c_void_p)]),
     "aim_set_macromodels": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
+    "aim_set_elem_type": (ctypes.c_int, [ctypes.c_void_p, _i32p, ctypes.c_void_p]),
     "aim_set_dmatrix": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _i32p, _i32p, _f64p]),
     "macro_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.c_void_p]),

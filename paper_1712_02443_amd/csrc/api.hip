@@ -650,6 +650,43 @@ int aim_build_host(const aim_surface* surface, const aim_array* array, aim_op** 
   return build_op(surface, array, out, false, nullptr);
 }
 
+int aim_set_elem_type(aim_op* op, const int32_t* elem_type, void* stream) {
+  if (!op || !elem_type) {
+    set_error("op and elem_type must not be NULL");
+    return AIM_EINVAL;
+  }
+  for (int m = 0; m < op->ne; ++m)
+    if (elem_type[m] < 0 || elem_type[m] >= op->n_types) {
+      set_error("element kind out of range");
+      return AIM_EINVAL;
+    }
+  std::vector<int> count(op->n_types, 0), start(op->n_types, 0), cols;
+  cols.reserve(size_t(op->ne) * op->R_max);
+  for (int t = 0; t < op->n_types; ++t) {
+    start[t] = int(cols.size());
+    std::vector<int> el;
+    for (int m = 0; m < op->ne; ++m)
+      if (elem_type[m] == t) el.push_back(m);
+    count[t] = int(el.size());
+    for (int r = 0; r < op->R_max; ++r)
+      for (int m : el) cols.push_back(r * op->ne + m);
+  }
+  if (op->device_ready) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(op->col_list, cols.data(), cols.size() * sizeof(int), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      set_error("element kinds: device copy failed");
+      return AIM_EDEVICE;
+    }
+  }
+  op->type_count.swap(count);
+  op->col_start.swap(start);
+  std::copy(elem_type, elem_type + op->ne, op->elem_type.begin());
+  aimm_macro_store_elem_types(op);
+  return AIM_OK;
+}
+
 
 // Device copies of one set of per-kind N x N blocks (host complex128 [n_types][N][N],
 // column-major): complex128 and complex64 with gemm_krows(N) columns per kind (zero

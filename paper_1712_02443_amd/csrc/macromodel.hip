@@ -904,6 +904,15 @@ void aimm_release_macro_store(const aim_op* op) {
   }
 }
 
+void aimm_macro_store_elem_types(const aim_op* op) {
+  std::lock_guard<std::mutex> lk(g_store_mu);
+  auto it = stores().find(op);
+  if (it == stores().end()) return;
+  MacroStore* st = it->second;
+  st->elem_off.assign(size_t(op->ne) + 1, 0);
+  for (int e = 0; e < op->ne; ++e) st->elem_off[e + 1] = st->elem_off[e] + st->n_scat[op->elem_type[e]];
+}
+
 static MacroStore* store_of(const aim_op* op) {
   std::lock_guard<std::mutex> lk(g_store_mu);
   auto it = stores().find(op);

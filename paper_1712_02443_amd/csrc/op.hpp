@@ -99,6 +99,8 @@ GemmArgs gemm_args_of(aim_op* op, int R);
 
 // frees the generated macromodel data of an op (R blocks, host copies); called by aim_destroy
 void aimm_release_macro_store(const aim_op* op);
+// recomputes the generated data's per-element scatterer offsets after the element kinds change
+void aimm_macro_store_elem_types(const aim_op* op);
 
 struct aim_op {
   aimm::Setup st;
