@@ -137,7 +137,8 @@ def test_preconditioned_gmres_alone_equals_in_batch(torch, prec):
 def test_full_size_preconditioned_mixed_solve(torch):
     """The 32 x 32 Jerusalem-cross array at the benchmark's settings (GMRES(50), 1e-6):
     the preconditioned mixed solve converges in under half the iterations of the plain
-    one, and its residual on rows sampled by the oracle is within the 2-norm bound."""
+    one, and its FP64 residual recomputed by the oracle over the whole vector meets the
+    tolerance."""
     from paper_1712_02443_amd import AIM_MIXED, AIM_PRECOND_BLOCK_JACOBI, AimOperator
     wl = make_workload(1)
     say(f"full-size preconditioned solve {wl.name}")
@@ -153,9 +154,8 @@ def test_full_size_preconditioned_mixed_solve(torch):
     assert sp_[0]["true_relres"] <= 1e-6
     assert 2 * sp_[0]["iters"] < s0[0]["iters"]
     o = OracleOperator(wl)
-    rng = np.random.default_rng(17)
-    rows = np.concatenate([rng.choice(wl.n_unknowns, 24, replace=False), [0, wl.n_unknowns - 1]])
     B = to_host(b)[0]
-    res_rows = B[rows] - o.matvec_rows(to_host(xp)[0], rows)
-    assert np.max(np.abs(res_rows)) <= 1e-6 * np.linalg.norm(B)
+    relres = np.linalg.norm(B - o.matvec(to_host(xp)[0])) / np.linalg.norm(B)
+    say(f"  oracle residual of the preconditioned mixed solve: {relres:.3e}")
+    assert relres <= 1.01e-6
     op.close()

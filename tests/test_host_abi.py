@@ -65,6 +65,41 @@ def test_host_near_field_matches_oracle(lib, case):
     op.close()
 
 
+def test_host_near_field_exact_entries_against_independent_quadrature(lib):
+    """The library's exact near-field entries (its pre-corrected values plus the grid part,
+    whose weights the oracle's pins fix by moment identities) against references that
+    share nothing with either Galerkin implementation: a 24 x 24 Gauss product rule of
+    the full kernel for pairs in different boxes (0.1 wavelength apart; the 7-point
+    rule is within 2e-3 there), and the pair rule on 64 sub-triangles of both triangles
+    for pairs in one box (the 7-point rule is within 3e-2 of it on touching pairs)."""
+    from galerkin_refs import plain_entry, refined_entry
+    from oracle import aim
+    from oracle.system import OracleOperator
+    wl = make_workload(0)
+    op = _host_op(wl)
+    rows, offs, cols, vals, offsets = op.near()
+    o = OracleOperator(wl, near=False)
+    rng = np.random.default_rng(0)
+    worst = {True: 0.0, False: 0.0}
+    for oi, (dx, dy) in enumerate(offsets):
+        pick = rng.choice(np.flatnonzero(offs == oi), 3, replace=False)
+        sh = np.array([dx, dy, 0]) * wl.pitch_cells
+        a, b = rows[pick], cols[pick]
+        grid = aim.grid_pair_values(o.W[:, a], o.s_local[a], o.W[:, b], (o.s_local + sh)[b], o.Gs, o.grid.shape,
+                                    wl.k, wl.eta)
+        exact = vals[pick] + grid
+        same_box = (int(dx), int(dy)) == (0, 0)
+        for i in range(len(pick)):
+            if same_box:
+                ref = refined_entry(o.geo, a[i], b[i], wl.k, wl.eta, levels=3)
+            else:
+                ref = plain_entry(o.geo, a[i], np.zeros(3), b[i], sh * wl.h, wl.k, wl.eta, n=24)
+            worst[same_box] = max(worst[same_box], abs(exact[i] - ref) / abs(ref))
+    assert worst[False] < 5e-3
+    assert worst[True] < 3e-2
+    op.close()
+
+
 def test_padded_lengths_are_5_smooth_and_long_enough(lib):
     for idx, kw in ((0, {}), (1, {}), (2, {}), (4, dict(px=64))):
         wl = make_workload(idx, **kw)

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 import scipy.special
 
+from galerkin_refs import plain_entry, refined_entry
 from oracle import aim
 from oracle.excitation import plane_wave_rhs
 from oracle.galerkin import efie_pairs, smooth_kernel, static_potentials
@@ -110,70 +111,13 @@ def test_smooth_kernel_limit_and_identity():
 
 
 # ---- Galerkin entries ------------------------------------------------------------
-def _plain_entry(geo, a, sa, b, sb, k, eta, n=20):
-    """G_ab by a high-order product rule of the full kernel (well separated pairs only)."""
-    bary, w = gauss_triangle_rule(n)
-    tot = 0.0
-    for sga, ta, pa in ((1, geo.tp, geo.pp), (-1, geo.tm, geo.pm)):
-        tva = geo.tri_vert[ta[a]] + sa
-        Aa = geo.tri_area[ta[a]]
-        ra = bary @ tva
-        la = sga * geo.length[a] / (2 * Aa) * (ra - (pa[a] + sa))
-        da = sga * geo.length[a] / Aa
-        for sgb, tb, pb in ((1, geo.tp, geo.pp), (-1, geo.tm, geo.pm)):
-            tvb = geo.tri_vert[tb[b]] + sb
-            Ab = geo.tri_area[tb[b]]
-            rb = bary @ tvb
-            lb = sgb * geo.length[b] / (2 * Ab) * (rb - (pb[b] + sb))
-            db = sgb * geo.length[b] / Ab
-            R = np.linalg.norm(ra[:, None, :] - rb[None, :, :], axis=-1)
-            G = np.exp(-1j * k * R) / (4 * math.pi * R)
-            integrand = (la @ lb.T - da * db / (k * k)) * G
-            tot += Aa * Ab * np.einsum("i,j,ij->", w, w, integrand)
-    return -1j * k * eta * tot
-
-
 def test_galerkin_far_pair_matches_high_order_rule(op0):
     geo, wl = op0.geo, op0.wl
     sa, sb = np.zeros(3), np.array([1.2, 0.6, 0.0])
     for a, b in [(0, 5), (17, 200), (140, 33)]:
         ours = efie_pairs(geo, sa, [a], geo, sb, [b], wl.k, wl.eta)[0]
-        ref = _plain_entry(geo, a, sa, b, sb, wl.k, wl.eta)
+        ref = plain_entry(geo, a, sa, b, sb, wl.k, wl.eta)
         assert abs(ours - ref) < 2e-5 * abs(ref)
-
-
-def _refined_entry(geo, a, b, k, eta, levels=2):
-    """G_ab with the test and source triangles split into 4^levels pieces (same rule per piece)."""
-    from oracle.galerkin import tri_pair_moments
-
-    def split(t):
-        out = [t]
-        for _ in range(levels):
-            nxt = []
-            for v in out:
-                m01, m12, m20 = 0.5 * (v[0] + v[1]), 0.5 * (v[1] + v[2]), 0.5 * (v[2] + v[0])
-                nxt += [np.array([v[0], m01, m20]), np.array([m01, v[1], m12]),
-                        np.array([m20, m12, v[2]]), np.array([m01, m12, m20])]
-            out = nxt
-        return np.array(out)
-
-    tot = 0.0
-    for sga, ta, pa in ((1, geo.tp, geo.pp), (-1, geo.tm, geo.pm)):
-        Aa = geo.tri_area[ta[a]]
-        for sgb, tb, pb in ((1, geo.tp, geo.pp), (-1, geo.tm, geo.pm)):
-            Ab = geo.tri_area[tb[b]]
-            A_sub = split(geo.tri_vert[ta[a]])
-            B_sub = split(geo.tri_vert[tb[b]])
-            I, J = np.meshgrid(np.arange(len(A_sub)), np.arange(len(B_sub)), indexing="ij")
-            ta_s, tb_s = A_sub[I.ravel()], B_sub[J.ravel()]
-            m0, m1, m2, m3 = tri_pair_moments(ta_s, tb_s, k)
-            aa = 0.5 * np.linalg.norm(np.cross(ta_s[:, 1] - ta_s[:, 0], ta_s[:, 2] - ta_s[:, 0]), axis=1)
-            P, Pb = pa[a], pb[b]
-            dot = m3 - m2 @ Pb - m1 @ P + np.dot(P, Pb) * m0
-            # the sub-triangle's own area weights its quadrature points
-            tot += sga * sgb * np.sum(aa * (geo.length[a] / (2 * Aa)) * (geo.length[b] / (2 * Ab)) * dot
-                                      - aa * (geo.length[a] / Aa) * (geo.length[b] / Ab) * m0 / (k * k))
-    return -1j * k * eta * tot
 
 
 @pytest.mark.parametrize("pair", [(0, 0), (0, 1), (5, 9), (100, 101)])
@@ -184,8 +128,8 @@ def test_galerkin_singular_pairs_converge_under_refinement(op0, pair):
     geo, wl = op0.geo, op0.wl
     a, b = pair
     ours = efie_pairs(geo, np.zeros(3), [a], geo, np.zeros(3), [b], wl.k, wl.eta)[0]
-    ref2 = _refined_entry(geo, a, b, wl.k, wl.eta, levels=2)
-    ref3 = _refined_entry(geo, a, b, wl.k, wl.eta, levels=3)
+    ref2 = refined_entry(geo, a, b, wl.k, wl.eta, levels=2)
+    ref3 = refined_entry(geo, a, b, wl.k, wl.eta, levels=3)
     assert abs(ref2 - ref3) < 2e-3 * abs(ref3)
     assert abs(ours - ref3) < 3e-2 * abs(ref3)
 
@@ -501,3 +445,41 @@ def test_oracle_without_near_field_keeps_the_grid_part():
         far.near_apply(x)
     with pytest.raises(RuntimeError):
         far.matvec(x)
+
+
+def test_row_products_equal_full_products():
+    """OracleOperator.matvec_rows and far_field_rows (the row-sampled products used for
+    arrays too large for a global near matrix) against the full matvec and far field, on a
+    three-kind 5 x 4 array, rows at both ends and in between."""
+    wl = make_workload(2, px=5, py=4, nrhs=1)
+    o = OracleOperator(wl)
+    x = wl.test_vectors(1)[0]
+    rows = np.concatenate([[0, 1, wl.n_unknowns - 1], np.random.default_rng(3).choice(wl.n_unknowns, 40,
+                                                                                       replace=False)])
+    full = o.matvec(x)
+    assert _rel(o.matvec_rows(x, rows), full[rows]) < 1e-13
+    u = o.macro_apply(x)
+    assert _rel(o.far_field_rows(u, rows), o.far_field(u)[rows]) < 1e-13
+
+
+def test_d_application_is_test_by_source():
+    """The operator applies D as (D x)_a = sum_b D_ab x_b with a the testing RWG function
+    and b the dual function (section IV): with the physical D of the box, d_apply of a unit
+    vector e_b is column b of <Lambda^_a, n x Lambda^'_b>, element by element."""
+    from oracle.macromodel import bc_dual_basis, dual_gram
+    from oracle.geometry import tri_area_normal
+    wl = make_workload(0)
+    mesh = wl.surface
+    geo = rwg_geometry(mesh.vert, mesh.tri, mesh.rwg)
+    _, n_out = tri_area_normal(geo.tri_vert)
+    D = dual_gram(geo, bc_dual_basis(mesh.vert, mesh.tri, mesh.rwg), n_out)
+    assert np.abs(D - D.T).max() > 1e-3 * np.abs(D).max()  # not symmetric: orientation matters
+    r, c = np.nonzero(D)
+    o = OracleOperator(wl, D=(r, c, D[r, c].astype(np.complex128)), near=False)
+    nb = geo.n_rwg
+    for b in (0, 7, nb - 1):
+        e = np.zeros(wl.n_unknowns, np.complex128)
+        e[nb + b] = 1.0  # element 1
+        y = o.d_apply(e)
+        assert np.abs(y[nb:2 * nb] - D[:, b]).max() == 0.0
+        assert np.abs(y[:nb]).max() == 0.0 and np.abs(y[2 * nb:]).max() == 0.0
