@@ -117,6 +117,26 @@ typedef struct {
  * is synchronised before the call returns.  *out is set only on success. */
 int aim_build_grid(const aim_surface* surface, const aim_array* array, void* stream, aim_op** out);
 
+/* Launch configuration of the product's kernels (what a tuner chooses; the results of
+ * every choice agree to rounding).  Fields of 0 (fft_b, interp tile) or -1 (flags) keep
+ * the current value in aim_set_tuning. */
+typedef struct {
+  int32_t fft_b[2];      /* ky lines per x-pass workgroup, [AIM_FP64, AIM_MIXED]: must divide
+                            the padded y length and fit one workgroup's LDS */
+  int32_t interp_tx, interp_ty;  /* elements per interpolation workgroup, tx ty <= 4 (lowered
+                                    at launch while the tile's potentials do not fit LDS) */
+  int32_t gemm_bf16;     /* mixed-path macromodel product: 1 split-BF16 MFMA (needs N % 8 == 0),
+                            0 FP32 MFMA */
+  int32_t fft_register;  /* 1 four-step passes of in-register DFTs (where compiled), 0 radix stages */
+} aim_tuning;
+
+/* Current launch configuration of the op. */
+int aim_get_tuning(const aim_op* op, aim_tuning* tuning);
+
+/* Set the launch configuration (AIM_EINVAL for a value the op cannot run, nothing changed).
+ * Takes effect from the next call; the op must have no work in flight. */
+int aim_set_tuning(aim_op* op, const aim_tuning* tuning);
+
 /* Change the kind of every element (host [py*px], values in [0, n_types)) of a built op,
  * keeping its grid, Green's-function spectrum, near field, macromodels, D and
  * preconditioner blocks, which do not depend on where each kind sits (section III: the
@@ -200,6 +220,12 @@ typedef struct {
                            (standard MoM on scatterer meshes: no macromodels or D
                            needed; block-Jacobi then wants blocks built with
                            M_t = -I and an empty D, which make them G_self^-1) */
+  int32_t graphs;       /* 1: each inner iteration's launches are captured once per
+                           iteration index as a HIP graph (on a library stream) and
+                           replayed on the caller's stream in later cycles and solves;
+                           the graphs stay with the op until its Krylov workspace, launch
+                           configuration or element kinds change.  0: launched one by
+                           one.  Results are bit-identical either way. */
   double tol;           /* relative residual target ||b - A x|| / ||b|| */
 } gmres_opts;
 

@@ -94,6 +94,17 @@ class AimOperator:
         check(self.lib.aim_set_dmatrix(self._op, r.shape[0], r.ctypes.data_as(_lib._i32p),
                                        c.ctypes.data_as(_lib._i32p), v.view(np.float64).ctypes.data_as(_lib._f64p)))
 
+    def tuning(self) -> dict:
+        t = _lib.AimTuning()
+        check(self.lib.aim_get_tuning(self._op, ctypes.byref(t)))
+        return {"fft_b": [int(t.fft_b[0]), int(t.fft_b[1])], "interp_tile": [int(t.interp_tx), int(t.interp_ty)],
+                "gemm_bf16": int(t.gemm_bf16), "fft_register": int(t.fft_register)}
+
+    def set_tuning(self, fft_b=(0, 0), interp_tile=(0, 0), gemm_bf16=-1, fft_register=-1):
+        t = _lib.AimTuning((ctypes.c_int32 * 2)(*fft_b), int(interp_tile[0]), int(interp_tile[1]), int(gemm_bf16),
+                           int(fft_register))
+        check(self.lib.aim_set_tuning(self._op, ctypes.byref(t)))
+
     def set_elem_type(self, elem_type, stream=None):
         """Re-assign the element kinds of this op (same lattice), keeping everything else."""
         et = np.ascontiguousarray(elem_type, dtype=np.int32)
@@ -267,13 +278,13 @@ class AimOperator:
         return E, rcs
 
     def gmres(self, b, x=None, *, restart=50, tol=1e-6, max_iters=1000, precision=AIM_FP64, check_every=1,
-              precond=0, system=AIM_FULL, stream=None):
+              precond=0, system=AIM_FULL, graphs=False, stream=None):
         R = self._check_vec(b, AIM_FP64)
         x0_given = x is not None
         if x is None:
             x = self._torch.empty_like(b)
         opts = GmresOpts(int(restart), int(max_iters), int(precision), int(x0_given), int(check_every), int(precond),
-                         int(system), float(tol))
+                         int(system), int(bool(graphs)), float(tol))
         stats = (GmresStat * R)()
         code = check(self.lib.gmres_solve(self._op, _dev_ptr(b), _dev_ptr(x), R, ctypes.byref(opts), stats,
                                           _stream(self._torch, stream)))

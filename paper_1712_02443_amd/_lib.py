@@ -44,10 +44,15 @@ class AimInfo(ctypes.Structure):
                 ("paths", ctypes.c_int32)]
 
 
+class AimTuning(ctypes.Structure):
+    _fields_ = [("fft_b", ctypes.c_int32 * 2), ("interp_tx", ctypes.c_int32), ("interp_ty", ctypes.c_int32),
+                ("gemm_bf16", ctypes.c_int32), ("fft_register", ctypes.c_int32)]
+
+
 class GmresOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("x0_given", ctypes.c_int32), ("check_every", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("system", ctypes.c_int32), ("tol", ctypes.c_double)]
+                ("system", ctypes.c_int32), ("graphs", ctypes.c_int32), ("tol", ctypes.c_double)]
 
 
 class GmresStat(ctypes.Structure):
@@ -64,6 +69,8 @@ EXPORTS = {
                                       ctypes.POINTER(ctypes.c_void_p)]),
     "aim_set_macromodels": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
     "aim_set_elem_type": (ctypes.c_int, [ctypes.c_void_p, _i32p, ctypes.c_void_p]),
+    "aim_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AimTuning)]),
+    "aim_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AimTuning)]),
     "aim_set_dmatrix": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _i32p, _i32p, _f64p]),
     "macro_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.c_void_p]),

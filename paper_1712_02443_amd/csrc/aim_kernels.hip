@@ -1322,6 +1322,30 @@ bool fft4_supported(int L) {
   return false;
 }
 
+static bool f4_factors(int L, int& l1, int& l2) {
+#define AIM_F4(A, B) \
+  if (L == A * B) {  \
+    l1 = A;          \
+    l2 = B;          \
+    return true;     \
+  }
+  AIM_F4_LENGTHS(AIM_F4)
+#undef AIM_F4
+  return false;
+}
+
+bool conv_fits(int Lx, int Ly, int nz, int B, bool f4, size_t elem, size_t lds_limit) {
+  if (B < 1 || Ly % B != 0) return false;
+  const size_t zb = size_t(B) * nz;
+  if (!f4) return elem * Lx * (1 + zb) <= lds_limit && elem * Ly * (1 + size_t(nz)) <= lds_limit;
+  int x1, x2, y1, y2;
+  if (!f4_factors(Lx, x1, x2) || !f4_factors(Ly, y1, y2)) return false;
+  // the same thread counts and LDS layouts as launch_convolve4_z
+  auto threads = [](size_t lines, int l1, int l2) { return (lines * std::max(l1, l2) + 63) / 64 * 64; };
+  if (threads(zb, x1, x2) > 512 || threads(nz, y1, y2) > 512) return false;
+  return elem * (Lx + zb * x1 * (x2 + 1)) <= lds_limit && elem * (Ly + size_t(nz) * y1 * (y2 + 1)) <= lds_limit;
+}
+
 hipError_t configure_lds(size_t bytes) {
   const int b = int(bytes);
   hipError_t e = hipSuccess, t;

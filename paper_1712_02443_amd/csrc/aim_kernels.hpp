@@ -25,6 +25,10 @@ struct ProjArgs {
 // FFT lengths L = L1 L2 with register-DFT (four-step) passes
 #define AIM_F4_LENGTHS(X) X(3, 9) X(5, 8) X(6, 9) X(8, 8) X(10, 20) X(16, 24) X(20, 20) X(25, 32)
 bool fft4_supported(int L);
+// whether the three FFT passes launch for padded lengths Lx, Ly, nz z nodes, B ky lines
+// per x-pass workgroup and the register-DFT (f4) or radix-stage passes, with elem-byte
+// complex values and lds_limit bytes of LDS per workgroup
+bool conv_fits(int Lx, int Ly, int nz, int B, bool f4, size_t elem, size_t lds_limit);
 
 struct ConvArgs {
   int R, nx, ny, nz, B;

@@ -140,8 +140,7 @@ static void fill_prec(aim_op* op, PrecData<T>& P) {
   if (const char* env = std::getenv("AIMM_FFT_B")) bmax = std::max(1, std::atoi(env));
   P.B = 1;
   for (int B = bmax; B >= 2; --B) {
-    const size_t lds = sizeof(cplx<T>) * size_t(op->Lx) * (1 + B * st.nz);
-    if (op->Ly % B == 0 && lds <= op->lds_max) {
+    if (conv_fits(op->Lx, op->Ly, st.nz, B, op->fft4, sizeof(cplx<T>), std::min<size_t>(op->lds_max, 160 * 1024))) {
       P.B = B;
       break;
     }
@@ -650,6 +649,78 @@ int aim_build_host(const aim_surface* surface, const aim_array* array, aim_op** 
   return build_op(surface, array, out, false, nullptr);
 }
 
+int aim_get_tuning(const aim_op* op, aim_tuning* t) {
+  if (!op || !t) {
+    set_error("op and tuning must not be NULL");
+    return AIM_EINVAL;
+  }
+  t->fft_b[0] = op->p64.B;
+  t->fft_b[1] = op->p32.B;
+  t->interp_tx = op->interp_tx > 0 ? op->interp_tx : 1;
+  t->interp_ty = op->interp_ty > 0 ? op->interp_ty : 1;
+  t->gemm_bf16 = op->gemm_bf16 ? 1 : 0;
+  t->fft_register = op->fft4 ? 1 : 0;
+  return AIM_OK;
+}
+
+int aim_set_tuning(aim_op* op, const aim_tuning* t) {
+  if (!op || !t) {
+    set_error("op and tuning must not be NULL");
+    return AIM_EINVAL;
+  }
+  if (!op->device_ready) {
+    set_error("tuning: host-only op");
+    return AIM_ESTATE;
+  }
+  if (t->fft_register == 1 && !(fft4_supported(op->Lx) && fft4_supported(op->Ly))) {
+    set_error("tuning: no register-DFT FFT pass for these padded lengths");
+    return AIM_EINVAL;
+  }
+  // the FFT passes must launch with the line blocks and pass kind in force afterwards
+  const int nz = op->st.nz;
+  const size_t lmax = std::min<size_t>(op->lds_max, 160 * 1024);
+  const bool f4 = t->fft_register >= 0 ? t->fft_register == 1 : op->fft4;
+  for (int p = 0; p < 2; ++p) {
+    if (t->fft_b[p] < 0) {
+      set_error("tuning: fft_b must be >= 0 (0 keeps the current value)");
+      return AIM_EINVAL;
+    }
+    const int B = t->fft_b[p] > 0 ? t->fft_b[p] : (p == 0 ? op->p64.B : op->p32.B);
+    const size_t elem = p == 0 ? sizeof(cplx<double>) : sizeof(cplx<float>);
+    if (!conv_fits(op->Lx, op->Ly, nz, B, f4, elem, lmax)) {
+      set_error("tuning: fft_b must divide the padded y length and its x-pass workgroup must fit (threads, LDS)");
+      return AIM_EINVAL;
+    }
+  }
+  if (t->interp_tx != 0 || t->interp_ty != 0) {
+    if (t->interp_tx < 1 || t->interp_ty < 1 || t->interp_tx * t->interp_ty > 4) {
+      set_error("tuning: interpolation tile must be tx x ty >= 1 with tx ty <= 4");
+      return AIM_EINVAL;
+    }
+    InterpArgs ia = interp_args<double>(op, 1);
+    ia.TX = t->interp_tx;
+    ia.TY = t->interp_ty;
+    if (interp_lds_bytes(ia, sizeof(cplx<double>)) > op->lds_max) {
+      set_error("tuning: the interpolation tile's potentials do not fit one workgroup's LDS");
+      return AIM_EINVAL;
+    }
+  }
+  if (t->gemm_bf16 == 1 && op->N % 8 != 0) {
+    set_error("tuning: the split-BF16 product needs N % 8 == 0");
+    return AIM_EINVAL;
+  }
+  if (t->fft_b[0] > 0) op->p64.B = t->fft_b[0];
+  if (t->fft_b[1] > 0) op->p32.B = t->fft_b[1];
+  if (t->interp_tx > 0) {
+    op->interp_tx = t->interp_tx;
+    op->interp_ty = t->interp_ty;
+  }
+  if (t->gemm_bf16 >= 0) op->gemm_bf16 = t->gemm_bf16 == 1;
+  if (t->fft_register >= 0) op->fft4 = t->fft_register == 1;
+  ++op->graph_epoch;  // captured GMRES iterations carry the old launch arguments
+  return AIM_OK;
+}
+
 int aim_set_elem_type(aim_op* op, const int32_t* elem_type, void* stream) {
   if (!op || !elem_type) {
     set_error("op and elem_type must not be NULL");
@@ -682,6 +753,7 @@ int aim_set_elem_type(aim_op* op, const int32_t* elem_type, void* stream) {
   }
   op->type_count.swap(count);
   op->col_start.swap(start);
+  ++op->graph_epoch;  // captured GMRES iterations carry the old kind counts
   std::copy(elem_type, elem_type + op->ne, op->elem_type.begin());
   aimm_macro_store_elem_types(op);
   return AIM_OK;

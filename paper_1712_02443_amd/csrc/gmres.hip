@@ -26,6 +26,8 @@ template <typename T>
 int precond_impl(aim_op* op, const cplx<T>* x, cplx<T>* y, int R, hipStream_t s);
 
 namespace {
+void drop_graphs(KrylovWork& K);
+
 
 constexpr int kBS = 256;
 constexpr int kE = 4;
@@ -751,6 +753,46 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
   std::vector<double> est_prev(R), rate_last(R, 0.0);
   std::vector<int> j_prev(R);
   bool x_zero = !o.x0_given;
+  // the launches of inner iteration j: (preconditioner,) product, two Gram-Schmidt passes
+  // with their reductions, and the Hessenberg / Givens step; no host synchronisation
+  auto inner = [&](int j, hipStream_t s) -> int {
+    const cplx<Tb>* uj = V + int64_t(j) * R * n;
+    cplx<Tb>* unext = V + int64_t(j + 1) * R * n;
+    const int nv = j + 1;
+    const cplx<float>* wlo = nullptr;
+    int irc;
+    if (pre) {
+      // right preconditioning: the product acts on z = P v_j (the residual buffer is free in a cycle)
+      irc = precond_impl<Tb>(op, uj, reinterpret_cast<cplx<Tb>*>(K.r), R, s);
+      if (irc) return irc;
+      uj = reinterpret_cast<const cplx<Tb>*>(K.r);
+    }
+    if (sizeof(Tb) == sizeof(double)) {
+      irc = matvec_impl<double>(op, reinterpret_cast<const cplx<double>*>(uj), K.w, R, sys, s);
+      if (irc) return irc;
+    } else {
+      irc = matvec_impl<float>(op, reinterpret_cast<const cplx<float>*>(uj), static_cast<cplx<float>*>(K.ylow), R,
+                               sys, s);
+      if (irc) return irc;
+      wlo = static_cast<const cplx<float>*>(K.ylow);
+    }
+    // classical Gram-Schmidt twice, in Gram form
+    int np = launch_step<Tb>(0, V, wlo, K.w, K.ib, m + 1, nullptr, 0, nullptr, K.part, n, nv, R, s);
+    GM_HIP(hipGetLastError());
+    GM_LAUNCH(k_reduce_dots, dim3(2 * nv * R), bs, 0, s, K.part, K.pq, np, 2 * nv, R, 2 * (m + 1), 0);
+    GM_LAUNCH(k_gram, dim3(R), bs, 0, s, K.pq, 2 * (m + 1), K.S, K.ib, K.hcol, K.cr, m, j, R);
+    np = launch_step<Tb>(1, V, wlo, K.w, K.ib, m + 1, K.cr, m + 1, unext, K.part, n, nv, R, s);
+    GM_HIP(hipGetLastError());
+    GM_LAUNCH(k_finish_step, dim3(R), bs, 0, s, K.part, np, K.ib, K.scal, K.H, K.cs, K.sn, K.g, K.hcol, K.active, m,
+              j, R);
+    return AIM_OK;
+  };
+  const bool use_graphs = o.graphs != 0;
+  if (K.graph_epoch != op->graph_epoch) {
+    drop_graphs(K);
+    K.graph_epoch = op->graph_epoch;
+  }
+  const int graph_key = (m << 4) | (sys << 1) | int(pre);
   for (;;) {
     // FP64 true residual r = b - A x (no product while x is still the zero start)
     int rc = x_zero ? AIM_OK : matvec_impl<double>(op, x, K.w, R, sys, s);
@@ -805,34 +847,31 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
       if (known) next_check = std::min(next_check, need_max);
     }
     for (int j = 0; j < budget_max; ++j) {
-      const cplx<Tb>* uj = V + int64_t(j) * R * n;
-      cplx<Tb>* unext = V + int64_t(j + 1) * R * n;
-      const int nv = j + 1;
-      const cplx<float>* wlo = nullptr;
-      if (pre) {
-        // right preconditioning: the product acts on z = P v_j (the residual buffer is free in a cycle)
-        rc = precond_impl<Tb>(op, uj, reinterpret_cast<cplx<Tb>*>(K.r), R, s);
-        if (rc) return rc;
-        uj = reinterpret_cast<const cplx<Tb>*>(K.r);
-      }
-      if (sizeof(Tb) == sizeof(double)) {
-        rc = matvec_impl<double>(op, reinterpret_cast<const cplx<double>*>(uj), K.w, R, sys, s);
-        if (rc) return rc;
+      if (use_graphs) {
+        // one captured graph per iteration index: replays the same launches with no
+        // per-kernel host overhead (captured on first use, replayed in later cycles and solves)
+        std::vector<hipGraphExec_t>& gv = K.graphs[graph_key];
+        if (gv.size() < size_t(m)) gv.resize(size_t(m), nullptr);
+        if (!gv[j]) {
+          if (!K.cap) GM_HIP(hipStreamCreateWithFlags(&K.cap, hipStreamNonBlocking));
+          GM_HIP(hipStreamBeginCapture(K.cap, hipStreamCaptureModeThreadLocal));
+          const int crc = inner(j, K.cap);
+          hipGraph_t graph = nullptr;
+          const hipError_t ce = hipStreamEndCapture(K.cap, &graph);
+          if (crc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return crc;
+          }
+          GM_HIP(ce);
+          const hipError_t ie = hipGraphInstantiate(&gv[j], graph, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(graph);
+          GM_HIP(ie);
+        }
+        GM_HIP(hipGraphLaunch(gv[j], s));
       } else {
-        rc = matvec_impl<float>(op, reinterpret_cast<const cplx<float>*>(uj), static_cast<cplx<float>*>(K.ylow), R,
-                                sys, s);
+        rc = inner(j, s);
         if (rc) return rc;
-        wlo = static_cast<const cplx<float>*>(K.ylow);
       }
-      // classical Gram-Schmidt twice, in Gram form
-      int np = launch_step<Tb>(0, V, wlo, K.w, K.ib, m + 1, nullptr, 0, nullptr, K.part, n, nv, R, s);
-      GM_HIP(hipGetLastError());
-      GM_LAUNCH(k_reduce_dots, dim3(2 * nv * R), bs, 0, s, K.part, K.pq, np, 2 * nv, R, 2 * (m + 1), 0);
-      GM_LAUNCH(k_gram, dim3(R), bs, 0, s, K.pq, 2 * (m + 1), K.S, K.ib, K.hcol, K.cr, m, j, R);
-      np = launch_step<Tb>(1, V, wlo, K.w, K.ib, m + 1, K.cr, m + 1, unext, K.part, n, nv, R, s);
-      GM_HIP(hipGetLastError());
-      GM_LAUNCH(k_finish_step, dim3(R), bs, 0, s, K.part, np, K.ib, K.scal, K.H, K.cs, K.sn, K.g, K.hcol, K.active, m,
-                j, R);
       j_end = j + 1;
       if (j_end >= next_check || j_end == budget_max) {
         GM_HIP(hipMemcpyAsync(jused, K.active, sizeof(int) * R, hipMemcpyDeviceToHost, s));
@@ -893,12 +932,21 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
   return all_conv ? AIM_OK : AIM_ENOCONV;
 }
 
+void drop_graphs(KrylovWork& K) {
+  for (auto& kv : K.graphs)
+    for (hipGraphExec_t g : kv.second)
+      if (g) (void)hipGraphExecDestroy(g);
+  K.graphs.clear();
+}
+
 void free_krylov(KrylovWork& K) {
+  drop_graphs(K);
   void* ps[] = {K.V,  K.w,  K.wlow, K.ylow, K.r,    K.H,    K.cs,     K.sn, K.g,
                 K.hcol, K.h2, K.part, K.scal, K.active, K.S, K.ib, K.pq, K.cr};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   if (K.hpin) (void)hipHostFree(K.hpin);
+  if (K.cap) (void)hipStreamDestroy(K.cap);
   K = KrylovWork{};
 }
 

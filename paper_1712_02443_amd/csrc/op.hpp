@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -87,6 +88,13 @@ struct KrylovWork {
   cplx<double>* h_g0 = nullptr;    // [R][restart+1]
   cplx<double>* h_gh = nullptr;    // [R][restart+1]
   double* h_ib0 = nullptr;         // [R][restart+1]
+  // captured inner iterations: key (precond, system, restart) -> one executable graph per
+  // iteration index j, valid for this workspace and the op's graph epoch
+  std::map<int, std::vector<hipGraphExec_t>> graphs;
+  int graph_epoch = -1;
+  // stream the iterations are captured on (the caller's stream may be the null stream,
+  // which cannot be captured); the graphs are then launched on the caller's stream
+  hipStream_t cap = nullptr;
 };
 
 void release_krylov(aim_op* op);
@@ -109,6 +117,7 @@ struct aim_op {
   std::vector<double> vert;
   std::vector<int32_t> tri, rwg;
   int device = 0;
+  int graph_epoch = 0;  // bumped when captured launch arguments change (element kinds)
   hipStream_t build_stream = nullptr;  // stream of aim_build_grid's uploads and kernels (during the call)
   int ne = 0, N = 0, R_max = 0, n_types = 0;
   int Lx = 0, Ly = 0;

@@ -154,7 +154,7 @@ def test_preconditioner_state_errors(lib):
     # device entry points still refuse a host-only op
     assert lib.precond_apply(op._op, ctypes.c_void_p(1), ctypes.c_void_p(2), 1, 0, None) == _lib.AIM_ESTATE
     # unknown preconditioner codes are rejected before any device work
-    opts = _lib.GmresOpts(10, 10, 0, 0, 1, 7, 0, 1e-6)
+    opts = _lib.GmresOpts(10, 10, 0, 0, 1, 7, 0, 0, 1e-6)
     stats = (_lib.GmresStat * 1)()
     assert lib.gmres_solve(op._op, ctypes.c_void_p(1), ctypes.c_void_p(2), 1, ctypes.byref(opts), stats,
                            None) == _lib.AIM_EINVAL
