@@ -505,10 +505,12 @@ static int build_op(const aim_surface* surface, const aim_array* array, aim_op**
       return AIM_OK;
     }
     op->device_ready = true;
-    // a default-priority stream for the near field, joined back by events
+    // a default-priority stream for the near field, joined back by events; they order
+    // work between two streams of this device only, so a device-scope release and
+    // acquire suffice (no system-scope cache write-back and invalidation)
     if (hipStreamCreateWithFlags(&op->s_aux, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess)
       throw std::runtime_error("stream or event creation failed");
     if (const char* env = std::getenv("AIMM_SERIAL")) {
       if (std::atoi(env) != 0) {
