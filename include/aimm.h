@@ -123,8 +123,9 @@ int aim_build_grid(const aim_surface* surface, const aim_array* array, void* str
 typedef struct {
   int32_t fft_b[2];      /* ky lines per x-pass workgroup, [AIM_FP64, AIM_MIXED]: must divide
                             the padded y length and fit one workgroup's LDS */
-  int32_t interp_tx, interp_ty;  /* elements per interpolation workgroup, tx ty <= 4 (lowered
-                                    at launch while the tile's potentials do not fit LDS) */
+  int32_t interp_tx, interp_ty;  /* elements per interpolation workgroup, tx ty <= 4; refused
+                                    if the tile's potentials do not fit one workgroup's LDS in
+                                    complex64, lowered at launch where they do not in complex128 */
   int32_t gemm_bf16;     /* mixed-path macromodel product: 1 split-BF16 MFMA (needs N % 8 == 0),
                             0 FP32 MFMA */
   int32_t fft_register;  /* 1 four-step passes of in-register DFTs (where compiled), 0 radix stages */

@@ -699,10 +699,11 @@ int aim_set_tuning(aim_op* op, const aim_tuning* t) {
       set_error("tuning: interpolation tile must be tx x ty >= 1 with tx ty <= 4");
       return AIM_EINVAL;
     }
-    InterpArgs ia = interp_args<double>(op, 1);
+    // checked in FP32; FP64 launches use the largest tile at most this size that fits
+    InterpArgs ia = interp_args<float>(op, 1);
     ia.TX = t->interp_tx;
     ia.TY = t->interp_ty;
-    if (interp_lds_bytes(ia, sizeof(cplx<double>)) > op->lds_max) {
+    if (interp_lds_bytes(ia, sizeof(cplx<float>)) > op->lds_max) {
       set_error("tuning: the interpolation tile's potentials do not fit one workgroup's LDS");
       return AIM_EINVAL;
     }
