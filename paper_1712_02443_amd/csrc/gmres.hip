@@ -723,7 +723,9 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
   const int nchs = int((n + kBS - 1) / kBS);  // chunks of the register-resident passes
   const dim3 gch(nch, R), bs(kBS), b64(64);
   cplx<Tb>* V = static_cast<cplx<Tb>*>(K.V);
-  GM_LAUNCH(k_residual, gch, bs, 0, s, b, (const cplx<double>*)nullptr, (cplx<double>*)nullptr, K.part, n);
+  // ||b|| (and, for the zero start, the first residual r = b into K.r)
+  GM_LAUNCH(k_residual, gch, bs, 0, s, b, (const cplx<double>*)nullptr, o.x0_given ? (cplx<double>*)nullptr : K.r,
+            K.part, n);
   GM_LAUNCH(k_finish_norm, dim3(R), bs, 0, s, K.part, K.scal + 3, nch, R, 4);
   if (!o.x0_given) GM_HIP(hipMemsetAsync(x, 0, sizeof(cplx<double>) * n * R, s));
   // host sides of the small transfers live in pinned memory (K.h_*); the host writes a
@@ -793,14 +795,45 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
     K.graph_epoch = op->graph_epoch;
   }
   const int graph_key = (m << 4) | (sys << 1) | int(pre);
+  // the launches of iteration j, captured as a graph or kernel by kernel
+  auto launch_iter = [&](int j) -> int {
+    if (!use_graphs) return inner(j, s);
+    // one captured graph per iteration index: replays the same launches with no
+    // per-kernel host overhead (captured on first use, replayed in later cycles and solves)
+    std::vector<hipGraphExec_t>& gv = K.graphs[graph_key];
+    if (gv.size() < size_t(m)) gv.resize(size_t(m), nullptr);
+    if (!gv[j]) {
+      if (!K.cap) GM_HIP(hipStreamCreateWithFlags(&K.cap, hipStreamNonBlocking));
+      GM_HIP(hipStreamBeginCapture(K.cap, hipStreamCaptureModeThreadLocal));
+      const int crc = inner(j, K.cap);
+      hipGraph_t graph = nullptr;
+      const hipError_t ce = hipStreamEndCapture(K.cap, &graph);
+      if (crc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return crc;
+      }
+      GM_HIP(ce);
+      const hipError_t ie = hipGraphInstantiate(&gv[j], graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      GM_HIP(ie);
+    }
+    GM_HIP(hipGraphLaunch(gv[j], s));
+    return AIM_OK;
+  };
   for (;;) {
-    // FP64 true residual r = b - A x (no product while x is still the zero start)
-    int rc = x_zero ? AIM_OK : matvec_impl<double>(op, x, K.w, R, sys, s);
-    if (rc) return rc;
-    GM_LAUNCH(k_residual, gch, bs, 0, s, b, x_zero ? (const cplx<double>*)nullptr : K.w, K.r, K.part, n);
-    GM_LAUNCH(k_finish_norm, dim3(R), bs, 0, s, K.part, K.scal, nch, R, 4);
-    GM_HIP(hipMemcpyAsync(hs, K.scal, sizeof(double) * 4 * R, hipMemcpyDeviceToHost, s));
-    GM_HIP(hipStreamSynchronize(s));
+    // FP64 true residual r = b - A x; for the zero start r = b is already in K.r and its
+    // norm on the host
+    int rc = AIM_OK;
+    if (x_zero) {
+      for (int r = 0; r < R; ++r) hs[4 * r] = bnorm[r];
+    } else {
+      rc = matvec_impl<double>(op, x, K.w, R, sys, s);
+      if (rc) return rc;
+      GM_LAUNCH(k_residual, gch, bs, 0, s, b, K.w, K.r, K.part, n);
+      GM_LAUNCH(k_finish_norm, dim3(R), bs, 0, s, K.part, K.scal, nch, R, 4);
+      GM_HIP(hipMemcpyAsync(hs, K.scal, sizeof(double) * 4 * R, hipMemcpyDeviceToHost, s));
+      GM_HIP(hipStreamSynchronize(s));
+    }
     bool any = false;
     int budget_max = 0;
     for (int r = 0; r < R; ++r) {
@@ -831,7 +864,10 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
       est_prev[r] = hs[4 * r];
       j_prev[r] = 0;
     }
+    // predicted_stop: every running right-hand side is predicted to pass its threshold
+    // by the next check (then no iteration is enqueued ahead of that check)
     int j_end = 0, next_check = std::min(check, budget_max);
+    bool predicted_stop = false;
     {
       bool known = true;
       int need_max = 1;
@@ -842,54 +878,51 @@ int gmres_impl(aim_op* op, const cplx<double>* b, cplx<double>* x, int R, const 
           break;
         }
         const int need = int(std::ceil(std::log(hs[4 * r + 1] / hs[4 * r]) / rate_last[r]));
+        if (need > check) known = false;
         need_max = std::max(need_max, std::min(std::max(need, 1), check));
       }
       if (known) next_check = std::min(next_check, need_max);
+      predicted_stop = known;
     }
+    int launched = 0;  // iterations of this cycle already enqueued
     for (int j = 0; j < budget_max; ++j) {
-      if (use_graphs) {
-        // one captured graph per iteration index: replays the same launches with no
-        // per-kernel host overhead (captured on first use, replayed in later cycles and solves)
-        std::vector<hipGraphExec_t>& gv = K.graphs[graph_key];
-        if (gv.size() < size_t(m)) gv.resize(size_t(m), nullptr);
-        if (!gv[j]) {
-          if (!K.cap) GM_HIP(hipStreamCreateWithFlags(&K.cap, hipStreamNonBlocking));
-          GM_HIP(hipStreamBeginCapture(K.cap, hipStreamCaptureModeThreadLocal));
-          const int crc = inner(j, K.cap);
-          hipGraph_t graph = nullptr;
-          const hipError_t ce = hipStreamEndCapture(K.cap, &graph);
-          if (crc) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return crc;
-          }
-          GM_HIP(ce);
-          const hipError_t ie = hipGraphInstantiate(&gv[j], graph, nullptr, nullptr, 0);
-          (void)hipGraphDestroy(graph);
-          GM_HIP(ie);
-        }
-        GM_HIP(hipGraphLaunch(gv[j], s));
-      } else {
-        rc = inner(j, s);
+      if (j >= launched) {
+        rc = launch_iter(j);
         if (rc) return rc;
+        launched = j + 1;
       }
       j_end = j + 1;
       if (j_end >= next_check || j_end == budget_max) {
         GM_HIP(hipMemcpyAsync(jused, K.active, sizeof(int) * R, hipMemcpyDeviceToHost, s));
         GM_HIP(hipMemcpyAsync(gh, K.g, sizeof(cplx<double>) * gl, hipMemcpyDeviceToHost, s));
-        GM_HIP(hipStreamSynchronize(s));
+        GM_HIP(hipEventRecord(K.ev_check, s));
+        // The device goes on with the next iteration while the host reads the flags.
+        // Should every right-hand side have stopped, that iteration changes nothing the
+        // solution uses: the Givens step leaves stopped right-hand sides alone, and its
+        // other outputs (u_{j+2}, s_{j+2}, scratch) lie past the columns the update reads.
+        if (!predicted_stop && j_end < budget_max) {
+          rc = launch_iter(j_end);
+          if (rc) return rc;
+          launched = j_end + 1;
+        }
+        GM_HIP(hipEventSynchronize(K.ev_check));
         bool all = true;
         int ahead = 1;
+        predicted_stop = true;
         for (int r = 0; r < R; ++r) {
           if (jused[r] != 0) continue;
           all = false;
           const cplx<double> gv = gh[size_t(r) * (m + 1) + j_end];
           const double est = std::sqrt(gv.re * gv.re + gv.im * gv.im), thr = hs[4 * r + 1];
           int need = check;
+          bool known = false;
           if (est > 0 && est < est_prev[r] && thr > 0) {
             const double rate = std::log(est / est_prev[r]) / double(j_end - j_prev[r]);
             need = int(std::ceil(std::log(thr / est) / rate));
             rate_last[r] = rate;
+            known = need <= check;
           }
+          if (!known) predicted_stop = false;
           ahead = std::max(ahead, std::min(std::max(need, 1), check));
           est_prev[r] = est;
           j_prev[r] = j_end;
@@ -947,6 +980,7 @@ void free_krylov(KrylovWork& K) {
     if (p) (void)hipFree(p);
   if (K.hpin) (void)hipHostFree(K.hpin);
   if (K.cap) (void)hipStreamDestroy(K.cap);
+  if (K.ev_check) (void)hipEventDestroy(K.ev_check);
   K = KrylovWork{};
 }
 
@@ -1004,6 +1038,10 @@ int ensure_krylov(aim_op* op, int R, int m, int prec) {
       K.h_gh = reinterpret_cast<cplx<double>*>(h + o4);
       K.h_ib0 = reinterpret_cast<double*>(h + o5);
     }
+  }
+  if (ok && hipEventCreateWithFlags(&K.ev_check, hipEventDisableTiming) != hipSuccess) {
+    K.ev_check = nullptr;
+    ok = false;
   }
   if (!ok) {
     free_krylov(K);

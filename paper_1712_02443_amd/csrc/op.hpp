@@ -95,6 +95,9 @@ struct KrylovWork {
   // stream the iterations are captured on (the caller's stream may be the null stream,
   // which cannot be captured); the graphs are then launched on the caller's stream
   hipStream_t cap = nullptr;
+  // recorded after a check's flag transfers: the host waits for it while the device
+  // runs the iteration enqueued after it
+  hipEvent_t ev_check = nullptr;
 };
 
 void release_krylov(aim_op* op);
