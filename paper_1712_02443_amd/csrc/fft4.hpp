@@ -156,6 +156,7 @@ __device__ __forceinline__ void fft4_lines(cplx<T>* buf, int nlines, const cplx<
   // pass A: one length-L1 DFT per (line, x2), then the twiddles W_L^{x2 k1}
   if (int(threadIdx.x) < nlines * L2) {
     const int line = threadIdx.x / L2, x2 = threadIdx.x - line * L2;
+    __builtin_assume(x2 >= 0 && x2 < L2);
     cplx<T>* b = buf + line * LD;
     cplx<T> v[L1];
 #pragma unroll
@@ -170,6 +171,7 @@ __device__ __forceinline__ void fft4_lines(cplx<T>* buf, int nlines, const cplx<
   // pass B: one length-L2 DFT per (line, k1); results go to the slots of k1 + L1 k2
   const bool act = int(threadIdx.x) < nlines * L1;
   const int line = threadIdx.x / L1, k1 = threadIdx.x - line * L1;
+  __builtin_assume(k1 >= 0 && k1 < L1);
   cplx<T> u[L2];
   if (act) {
     const cplx<T>* b = buf + line * LD + k1 * P;
