@@ -863,8 +863,10 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const cplx<float>* __restrict_
 // m = bf16(v - h), l = bf16(v - h - m); each difference is exact in FP32), and a real
 // product uses the six bf16 products h.h + h.m + m.h + h.l + l.h + m.m, accumulated
 // in FP32 by v_mfma_f32_32x32x16_bf16 (the dropped terms are below 2^-24 relative).
-// Complex steps take three real products as in the FP32 kernel.  M is pre-split on
-// the host into 9 planes (h, m, l of re, im, re + im) laid out [plane][k / 8][row][8]
+// Complex steps take the four real products re.re - im.im and re.im + im.re (four
+// rather than the FP32 kernel's three: the kernel is bound by the bytes of M it
+// streams, and the (re + im) planes would add half of them again).  M is pre-split on
+// the host into 6 planes (h, m, l of re, then of im) laid out [plane][k / 8][row][8]
 // so a lane's 8 consecutive k of one row are one 16-byte load; X is split on the fly
 // (8 consecutive k of one column, 64 contiguous bytes, per lane).
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -892,12 +894,12 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(const u32x4* __restrict__ M
   const int colj = max(cols[lane & 31], 0);
   const int kq = a.Kq, kb = w * kq, ke = kb + kq;
   const int KB = a.Krows / 8;
-  const u32x4* Mt = Mb + int64_t(t) * 9 * KB * N;
+  const u32x4* Mt = Mb + int64_t(t) * 6 * KB * N;
   const cplx<float>* xc = X + int64_t(colj) * N;
-  // lane's 8 k of the chunk at k0: A rows ir, k0 + 8 hk .. + 7 (9 planes); B column colj
+  // lane's 8 k of the chunk at k0: A rows ir, k0 + 8 hk .. + 7 (6 planes); B column colj
   auto load_a = [&](int k0, u32x4* av) {
 #pragma unroll
-    for (int p = 0; p < 9; ++p) av[p] = Mt[(int64_t(p) * KB + (k0 >> 3) + hk) * N + ir];
+    for (int p = 0; p < 6; ++p) av[p] = Mt[(int64_t(p) * KB + (k0 >> 3) + hk) * N + ir];
   };
   auto load_b = [&](int k0, cplx<float>* bv) {
     const int kk = k0 + 8 * hk;
@@ -905,7 +907,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(const u32x4* __restrict__ M
 #pragma unroll
     for (int u = 0; u < 8; ++u) bv[u] = src[u];
   };
-  f32x16 accRR = {}, accII = {}, accSS = {};
+  f32x16 accRe = {}, accIm = {};
   auto mma6 = [](f32x16 acc, const bf16x8* a3, const bf16x8* b3) {
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[0], b3[0], acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[0], b3[1], acc, 0, 0, 0);
@@ -915,7 +917,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(const u32x4* __restrict__ M
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[1], b3[1], acc, 0, 0, 0);
     return acc;
   };
-  u32x4 ca[9], na[9];
+  u32x4 ca[6], na[6];
   cplx<float> cb[8], nb[8];
   load_a(kb, ca);
   load_b(kb, cb);
@@ -924,7 +926,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(const u32x4* __restrict__ M
       load_a(k0 + 16, na);
       load_b(k0 + 16, nb);
     }
-    bf16x8 br[3], bi[3], bs[3];
+    bf16x8 br[3], bi[3], bn[3];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       __bf16 h, m, l;
@@ -936,23 +938,26 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(const u32x4* __restrict__ M
       bi[0][u] = h;
       bi[1][u] = m;
       bi[2][u] = l;
-      split3(cb[u].re + cb[u].im, h, m, l);
-      bs[0][u] = h;
-      bs[1][u] = m;
-      bs[2][u] = l;
     }
-    bf16x8 ar[3], ai[3], as[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {  // -im, exactly: the sign bits of its split terms flipped
+      u32x4 t = __builtin_bit_cast(u32x4, bi[q]);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) t[c] ^= 0x80008000u;
+      bn[q] = __builtin_bit_cast(bf16x8, t);
+    }
+    bf16x8 ar[3], ai[3];
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
       ar[p] = __builtin_bit_cast(bf16x8, ca[p]);
       ai[p] = __builtin_bit_cast(bf16x8, ca[3 + p]);
-      as[p] = __builtin_bit_cast(bf16x8, ca[6 + p]);
     }
-    accRR = mma6(accRR, ar, br);
-    accII = mma6(accII, ai, bi);
-    accSS = mma6(accSS, as, bs);
+    accRe = mma6(accRe, ar, br);
+    accRe = mma6(accRe, ai, bn);
+    accIm = mma6(accIm, ar, bi);
+    accIm = mma6(accIm, ai, br);
 #pragma unroll
-    for (int p = 0; p < 9; ++p) ca[p] = na[p];
+    for (int p = 0; p < 6; ++p) ca[p] = na[p];
 #pragma unroll
     for (int u = 0; u < 8; ++u) cb[u] = nb[u];
   }
@@ -960,7 +965,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(const u32x4* __restrict__ M
   for (int r = 0; r < 16; ++r) {
     const int row = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);  // 32 x 32 MFMA output row
     part[(w * kGemmRows + row) * (kGemmCols + 1) + (lane & 31)] =
-        cmk<float>(accRR[r] - accII[r], accSS[r] - accRR[r] - accII[r]);
+        cmk<float>(accRe[r], accIm[r]);
   }
   __syncthreads();
   gemm_reduce_store<float>(part, U, colbase, N, a.ne, i0);

@@ -766,7 +766,7 @@ int aim_set_elem_type(aim_op* op, const int32_t* elem_type, void* stream) {
 // Device copies of one set of per-kind N x N blocks (host complex128 [n_types][N][N],
 // column-major): complex128 and complex64 with gemm_krows(N) columns per kind (zero
 // past N), and, for N % 8 == 0, the split-BF16 planes
-// [h, m, l of re; of im; of re + im][k / 8][row][k % 8] of the complex64 values.
+// [h, m, l of re; of im][k / 8][row][k % 8] of the complex64 values.
 // Allocates on first use; throws std::bad_alloc or std::runtime_error.
 static void upload_blocks(aim_op* op, const cd* M, cplx<double>*& d64, cplx<float>*& d32, void*& db) {
   const size_t N = size_t(op->N), kr = size_t(gemm_krows(op->N));
@@ -789,14 +789,14 @@ static void upload_blocks(aim_op* op, const cd* M, cplx<double>*& d64, cplx<floa
       hipMemcpy(d32, m32.data(), n * sizeof(cplx<float>), hipMemcpyHostToDevice) != hipSuccess)
     throw std::runtime_error("hipMemcpy of the block set failed");
   if (op->N % 8 != 0) return;
-  const size_t KB = kr / 8, per = 9 * KB * N * 8;
+  const size_t KB = kr / 8, per = 6 * KB * N * 8;
   std::vector<uint16_t> mb(size_t(op->n_types) * per, 0);
   for (size_t t = 0; t < size_t(op->n_types); ++t)
     for (size_t k = 0; k < kr; ++k)
       for (size_t i = 0; i < N; ++i) {
         const cplx<float> v = m32[t * kr * N + k * N + i];
-        const float comp[3] = {v.re, v.im, v.re + v.im};
-        for (int c = 0; c < 3; ++c) {
+        const float comp[2] = {v.re, v.im};
+        for (int c = 0; c < 2; ++c) {
           uint16_t part3[3];
           split_bf16(comp[c], part3);
           for (int q = 0; q < 3; ++q) mb[t * per + ((size_t(3 * c + q) * KB + k / 8) * N + i) * 8 + k % 8] = part3[q];
@@ -1168,7 +1168,7 @@ size_t aim_footprint_bytes(const aim_surface* surface, const aim_array* array, i
   b += R * 4 * nx * Ly * ez * 16;                    // spectrum pass
   b += (Lx / 2 + 1) * (Ly / 2 + 1) * ez * 24;        // kernel spectrum, both precisions
   b += size_t(array->n_types) * N * N * 24;          // macromodels
-  b += size_t(array->n_types) * 9 * (4 * ((N + 63) / 64 * 16) + 16) * N * 2;  // their split-BF16 planes
+  b += size_t(array->n_types) * 6 * (4 * ((N + 63) / 64 * 16) + 16) * N * 2;  // their split-BF16 planes
   b += N * 600 * 28 + N * q * q * q * 4 * 24;        // near field (upper estimate) and weights
   const size_t vec = precision == AIM_FP64 ? 16 : 8;
   b += size_t(restart + 1) * size_t(nrhs) * n * vec;  // Krylov basis

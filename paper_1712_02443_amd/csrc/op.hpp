@@ -140,7 +140,7 @@ struct aim_op {
   bool near_mfma = true;
   bool fft4 = false;  // register-DFT FFT passes
   bool gemm_bf16 = false;  // mixed-path macromodel product on the bf16 matrix cores (split in three)
-  void* Mb = nullptr;      // [n_types][9 planes][Krows / 8][N][8] bf16
+  void* Mb = nullptr;      // [n_types][6 planes][Krows / 8][N][8] bf16
   int interp_tx = 0, interp_ty = 0;  // interpolation tile (0 = automatic)
   int *nbr = nullptr, *d_colT = nullptr, *rev_x = nullptr, *rev_y = nullptr, *col_list = nullptr;
   aimm::PrecData<double> p64;
