@@ -129,6 +129,8 @@ typedef struct {
   int32_t gemm_bf16;     /* mixed-path macromodel product: 1 split-BF16 MFMA (needs N % 8 == 0),
                             0 FP32 MFMA */
   int32_t fft_register;  /* 1 four-step passes of in-register DFTs (where compiled), 0 radix stages */
+  int32_t near_block[2]; /* near field on the matrix cores, [AIM_FP64, AIM_MIXED]: blocks of 16
+                            elements per workgroup, 1 or 2 (two share every coefficient load) */
 } aim_tuning;
 
 /* Current launch configuration of the op. */

@@ -1,5 +1,6 @@
 """Autotuner of the product's launch configuration (aim_set_tuning): x-pass FFT line
-block, interpolation element tile, macromodel GEMM kernel and FFT pass kind.
+block, interpolation element tile, macromodel GEMM kernel, FFT pass kind and near-field
+element blocks per workgroup.
 
 For one op, right-hand-side count and precision it times every admissible candidate
 with HIP events around back-to-back products, keeps only candidates whose product
@@ -44,14 +45,15 @@ def _candidates(op, precision):
     tiles = [(1, 1), (2, 1), (1, 2), (2, 2)]
     gemm = [cur["gemm_bf16"]] if precision == AIM_FP64 else ([0, 1] if inf["n_rwg"] % 8 == 0 else [0])
     fftk = [0, 1] if cur["fft_register"] or (inf["paths"] & 1) else [0]
-    for b, t, g, f in itertools.product(fft_b, tiles, gemm, fftk):
-        yield {"fft_b": b, "interp_tile": list(t), "gemm_bf16": g, "fft_register": f}
+    for b, t, g, f, nb in itertools.product(fft_b, tiles, gemm, fftk, (1, 2)):
+        yield {"fft_b": b, "interp_tile": list(t), "gemm_bf16": g, "fft_register": f, "near_block": nb}
 
 
 def _apply(op, cand, precision):
     fb = [cand["fft_b"], 0] if precision == AIM_FP64 else [0, cand["fft_b"]]
+    nb = cand.get("near_block", 0)
     op.set_tuning(fft_b=fb, interp_tile=cand["interp_tile"], gemm_bf16=cand["gemm_bf16"],
-                  fft_register=cand["fft_register"])
+                  fft_register=cand["fft_register"], near_block=[nb, 0] if precision == AIM_FP64 else [0, nb])
 
 
 def tune(op, nrhs: int = 1, precision: int = AIM_MIXED, cache_path: str | None = DEFAULT_CACHE, reps: int = 10,
@@ -104,7 +106,7 @@ def tune(op, nrhs: int = 1, precision: int = AIM_MIXED, cache_path: str | None =
             best = (us, cand, err)
     if best is None:
         op.set_tuning(fft_b=start["fft_b"], interp_tile=start["interp_tile"], gemm_bf16=start["gemm_bf16"],
-                      fft_register=start["fft_register"])
+                      fft_register=start["fft_register"], near_block=start["near_block"])
         raise RuntimeError("no candidate launch configuration passed the accuracy check")
     _apply(op, best[1], precision)
     if cache_path:

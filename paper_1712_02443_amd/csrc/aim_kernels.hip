@@ -579,28 +579,34 @@ __device__ __forceinline__ int mfma16_row(int lane, int r) {
   return sizeof(T) == 4 ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r;
 }
 
-template <typename T>
+template <typename T, int EB>
 __global__ void __launch_bounds__(256) k_near_mfma(const cplx<T>* __restrict__ uT, cplx<T>* __restrict__ nf,
                                                    NearArgs a, const cplx<T>* __restrict__ grp_A) {
-  // four waves, one per quarter of the union columns, over 16 elements (twice the waves
-  // of two K halves x two element halves, measured 5% faster); the group's column list
-  // is staged in LDS so the operand gathers wait on LDS only
+  // four waves, one per quarter of the union columns, over EB blocks of 16 elements
+  // (EB blocks share every coefficient operand load); the group's column list is
+  // staged in LDS so the operand gathers wait on LDS only
   using M = NearMfma<T>;
-  __shared__ cplx<T> tile[4][kNearGroupDev][17];
+  __shared__ cplx<T> tile[EB][4][kNearGroupDev][17];
   extern __shared__ int cols_s[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int kh = wave;
-  const int mblk = blockIdx.x * 16, g = blockIdx.y, r = blockIdx.z;
+  const int mblk = blockIdx.x * 16 * EB, g = blockIdx.y, r = blockIdx.z;
   const int jcol = lane & 15, kq = lane >> 4;
-  const int mb = mblk + jcol;
-  const int ix = mb % a.px, iy = mb / a.px;
   // bit (dy + 2) 5 + (dx + 2): the neighbour at lattice offset (dx, dy) exists
-  unsigned vmask = 0;
-  if (mb < a.ne)
-    for (int dy = -2; dy <= 2; ++dy)
-      for (int dx = -2; dx <= 2; ++dx)
-        if (ix + dx >= 0 && ix + dx < a.px && iy + dy >= 0 && iy + dy < a.py) vmask |= 1u << ((dy + 2) * 5 + dx + 2);
-  const cplx<T>* ur = uT + int64_t(r) * a.N * a.ne + mb;
+  unsigned vmask[EB];
+  const cplx<T>* ur[EB];
+#pragma unroll
+  for (int e = 0; e < EB; ++e) {
+    const int mb = mblk + 16 * e + jcol;
+    const int ix = mb % a.px, iy = mb / a.px;
+    unsigned vm = 0;
+    if (mb < a.ne)
+      for (int dy = -2; dy <= 2; ++dy)
+        for (int dx = -2; dx <= 2; ++dx)
+          if (ix + dx >= 0 && ix + dx < a.px && iy + dy >= 0 && iy + dy < a.py) vm |= 1u << ((dy + 2) * 5 + dx + 2);
+    vmask[e] = vm;
+    ur[e] = uT + int64_t(r) * a.N * a.ne + mb;
+  }
   const cplx<T>* zero = static_cast<const cplx<T>*>(a.zero);
   // the group's columns plus one prefetch batch past them (the next group's or the
   // zero tail): every load below is unconditional, so the prefetch stays in flight
@@ -611,45 +617,56 @@ __global__ void __launch_bounds__(256) k_near_mfma(const cplx<T>* __restrict__ u
   const int k0 = kh * quarter, k1 = k0 + quarter;
   const cplx<T>* Ag = grp_A + int64_t(g0) * kNearGroupDev;
   // three real products per complex step: re.re, im.im and (re + im).(re + im)
-  typename M::acc_t accRR = {}, accII = {}, accSS = {};
+  typename M::acc_t accRR[EB] = {}, accII[EB] = {}, accSS[EB] = {};
   constexpr int P = 4;  // K-steps per batch; the next batch is loaded ahead (8 measured 2% slower in FP32)
-  auto fetch = [&](int k, cplx<T>& av, cplx<T>& bv) {
+  auto fetch = [&](int k, cplx<T>& av, cplx<T>(&bv)[EB]) {
     const int col = cols_s[k + kq];
-    const bool ok = (vmask >> (col & 31)) & 1u;
-    bv = *(ok ? ur + (col >> 5) : zero);  // absent neighbours read a zero
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const bool ok = (vmask[e] >> (col & 31)) & 1u;
+      bv[e] = *(ok ? ur[e] + (col >> 5) : zero);  // absent neighbours read a zero
+    }
     av = Ag[int64_t(k + kq) * kNearGroupDev + jcol];
   };
-  cplx<T> ca[P], cb[P];
+  cplx<T> ca[P], cb[P][EB];
 #pragma unroll
   for (int u = 0; u < P; ++u) fetch(k0 + 4 * u, ca[u], cb[u]);
   for (int k = k0; k < k1; k += 4 * P) {
-    cplx<T> na[P], nb[P];
+    cplx<T> na[P], nb[P][EB];
 #pragma unroll
     for (int u = 0; u < P; ++u) fetch(k + 4 * P + 4 * u, na[u], nb[u]);
 #pragma unroll
     for (int u = 0; u < P; ++u) {
-      accRR = M::mma(ca[u].re, cb[u].re, accRR);
-      accII = M::mma(ca[u].im, cb[u].im, accII);
-      accSS = M::mma(ca[u].re + ca[u].im, cb[u].re + cb[u].im, accSS);
+      const T as = ca[u].re + ca[u].im;
+#pragma unroll
+      for (int e = 0; e < EB; ++e) {
+        accRR[e] = M::mma(ca[u].re, cb[u][e].re, accRR[e]);
+        accII[e] = M::mma(ca[u].im, cb[u][e].im, accII[e]);
+        accSS[e] = M::mma(as, cb[u][e].re + cb[u][e].im, accSS[e]);
+      }
     }
 #pragma unroll
     for (int u = 0; u < P; ++u) {
       ca[u] = na[u];
-      cb[u] = nb[u];
+#pragma unroll
+      for (int e = 0; e < EB; ++e) cb[u][e] = nb[u][e];
     }
   }
 #pragma unroll
-  for (int rr = 0; rr < 4; ++rr)
-    tile[kh][mfma16_row<T>(lane, rr)][jcol] =
-        cmk<T>(accRR[rr] - accII[rr], accSS[rr] - accRR[rr] - accII[rr]);
+  for (int e = 0; e < EB; ++e)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+      tile[e][kh][mfma16_row<T>(lane, rr)][jcol] =
+          cmk<T>(accRR[e][rr] - accII[e][rr], accSS[e][rr] - accRR[e][rr] - accII[e][rr]);
   __syncthreads();
   // output in group-slot order: 16 consecutive slots per element
   const int s0 = g * kNearGroupDev;
-  for (int idx = threadIdx.x; idx < 16 * kNearGroupDev; idx += 256) {
+  for (int idx = threadIdx.x; idx < 16 * EB * kNearGroupDev; idx += 256) {
     const int mm = idx / kNearGroupDev, nn = idx - mm * kNearGroupDev;
+    const int e = mm >> 4, me = mm & 15;
     if (mblk + mm < a.ne)
       nf[(int64_t(r) * a.ne + mblk + mm) * a.ld_nf + s0 + nn] =
-          cadd(cadd(tile[0][nn][mm], tile[1][nn][mm]), cadd(tile[2][nn][mm], tile[3][nn][mm]));
+          cadd(cadd(tile[e][0][nn][me], tile[e][1][nn][me]), cadd(tile[e][2][nn][me], tile[e][3][nn][me]));
   }
 }
 
@@ -1222,9 +1239,16 @@ hipError_t launch_near(const cplx<T>* uT, cplx<T>* nf, const NearArgs& a, const 
   if (a.grp_A) {
     // element blocks fastest, so consecutive workgroups (spread over the XCDs) share
     // the rows of u they read
-    const dim3 g((a.ne + 15) / 16, (a.N + kNearGroupDev - 1) / kNearGroupDev, a.R);
-    hipLaunchKernelGGL(k_near_mfma<T>, g, dim3(256), sizeof(int) * size_t(a.grp_max_cols + kNearColTailDev), s, uT,
-                       nf, a, reinterpret_cast<const cplx<T>*>(a.grp_A));
+    const size_t lds = sizeof(int) * size_t(a.grp_max_cols + kNearColTailDev);
+    if (a.eb == 2) {
+      const dim3 g((a.ne + 31) / 32, (a.N + kNearGroupDev - 1) / kNearGroupDev, a.R);
+      hipLaunchKernelGGL((k_near_mfma<T, 2>), g, dim3(256), lds, s, uT, nf, a,
+                         reinterpret_cast<const cplx<T>*>(a.grp_A));
+    } else {
+      const dim3 g((a.ne + 15) / 16, (a.N + kNearGroupDev - 1) / kNearGroupDev, a.R);
+      hipLaunchKernelGGL((k_near_mfma<T, 1>), g, dim3(256), lds, s, uT, nf, a,
+                         reinterpret_cast<const cplx<T>*>(a.grp_A));
+    }
   } else {
     const dim3 g((a.N + kNearRows - 1) / kNearRows, (a.ne + 63) / 64, a.R);
     hipLaunchKernelGGL(k_near<T>, g, dim3(256), 0, s, uT, nf, a, near_val);

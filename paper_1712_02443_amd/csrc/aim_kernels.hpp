@@ -60,6 +60,7 @@ struct NearArgs {
   const void* zero;    // one zero complex value (read for absent neighbours)
   int grp_max_cols;    // largest column count of a group (LDS staging of its columns)
   int ld_nf;           // slots per element of the output (groups x kNearGroupDev)
+  int eb;              // matrix-core path: blocks of 16 elements per workgroup (1 or 2)
 };
 
 struct InterpArgs {

@@ -327,6 +327,7 @@ int matvec_impl(aim_op* op, const cplx<T>* x, cplx<T>* y, int R, int flags, hipS
   // with the projection and the FFT passes (in order on one stream when timing kernels)
   NearArgs na = near_args(op, R);
   if (op->near_mfma) na.grp_A = P.grpA;
+  na.eb = op->near_eb[sizeof(T) == sizeof(double) ? 0 : 1];
   const bool fork = !ev && op->s_aux && flags != AIM_FAR_ONLY;
   if (fork) {
     AIM_HIP(hipEventRecord(op->ev_fork, s));
@@ -397,6 +398,7 @@ static int time_kernels(aim_op* op, const cplx<T>* x, cplx<T>* y, int R, int rep
   }
   NearArgs na = near_args(op, R);
   if (op->near_mfma) na.grp_A = P.grpA;
+  na.eb = op->near_eb[sizeof(T) == sizeof(double) ? 0 : 1];
   const GemmArgs ga = gemm_args(op, R);
   const ProjArgs pa = proj_args(op, R);
   const InterpArgs ia = interp_args<T>(op, R);
@@ -662,6 +664,8 @@ int aim_get_tuning(const aim_op* op, aim_tuning* t) {
   t->interp_ty = op->interp_ty > 0 ? op->interp_ty : 1;
   t->gemm_bf16 = op->gemm_bf16 ? 1 : 0;
   t->fft_register = op->fft4 ? 1 : 0;
+  t->near_block[0] = op->near_eb[0];
+  t->near_block[1] = op->near_eb[1];
   return AIM_OK;
 }
 
@@ -708,6 +712,11 @@ int aim_set_tuning(aim_op* op, const aim_tuning* t) {
       return AIM_EINVAL;
     }
   }
+  for (int p = 0; p < 2; ++p)
+    if (t->near_block[p] < 0 || t->near_block[p] > 2) {
+      set_error("tuning: near_block must be 1 or 2 element blocks per workgroup (0 keeps the current value)");
+      return AIM_EINVAL;
+    }
   if (t->gemm_bf16 == 1 && op->N % 8 != 0) {
     set_error("tuning: the split-BF16 product needs N % 8 == 0");
     return AIM_EINVAL;
@@ -720,6 +729,8 @@ int aim_set_tuning(aim_op* op, const aim_tuning* t) {
   }
   if (t->gemm_bf16 >= 0) op->gemm_bf16 = t->gemm_bf16 == 1;
   if (t->fft_register >= 0) op->fft4 = t->fft_register == 1;
+  for (int p = 0; p < 2; ++p)
+    if (t->near_block[p] > 0) op->near_eb[p] = t->near_block[p];
   ++op->graph_epoch;  // captured GMRES iterations carry the old launch arguments
   return AIM_OK;
 }
