@@ -65,9 +65,12 @@ def tune(op, nrhs: int = 1, precision: int = AIM_MIXED, cache_path: str | None =
     key = shape_key(op, nrhs, precision)
     cache = _load(cache_path) if cache_path else {}
     if key in cache:
-        _apply(op, cache[key]["tuning"], precision)
-        return {"key": key, "tuning": cache[key]["tuning"], "us": cache[key]["us"], "cached": True,
-                "tried": 0, "rejected": 0}
+        try:
+            _apply(op, cache[key]["tuning"], precision)
+            return {"key": key, "tuning": cache[key]["tuning"], "us": cache[key]["us"], "cached": True,
+                    "tried": 0, "rejected": 0}
+        except (AimError, KeyError, TypeError):
+            pass  # an entry this library refuses (or an older format): search again and replace it
     rng = np.random.default_rng(seed)
     xh = rng.standard_normal((nrhs, op.n)) + 1j * rng.standard_normal((nrhs, op.n))
     x64 = torch.from_numpy(xh).to("cuda")

@@ -58,6 +58,25 @@ def test_tuned_product_matches_oracle_and_cache_is_reused(torch, tmp_path, prec)
     op2.close()
 
 
+def test_unusable_cache_entry_is_searched_again(torch, tmp_path):
+    """A cached choice the library refuses (here a near-field blocking it does not offer)
+    leaves the op's configuration alone, and the tuner searches again and replaces it."""
+    import json
+    from paper_1712_02443_amd.autotune import shape_key, tune
+    wl = make_workload(1, px=5, py=4, nrhs=1)
+    op = make(wl)
+    cache = str(tmp_path / "tuning.json")
+    bad = {"fft_b": 1, "interp_tile": [1, 1], "gemm_bf16": 1, "fft_register": 1, "near_block": 7}
+    with open(cache, "w") as f:
+        json.dump({shape_key(op, 1, 1): {"tuning": bad, "us": 1.0}}, f)
+    res = tune(op, nrhs=1, precision=1, cache_path=cache, reps=2)
+    say(f"re-tuned {res['key']}: {res['tuning']}, tried {res['tried']}")
+    assert not res["cached"] and res["tried"] > 1 and res["tuning"]["near_block"] in (1, 2)
+    with open(cache) as f:
+        assert json.load(f)[res["key"]]["tuning"] == res["tuning"]
+    op.close()
+
+
 def test_invalid_tuning_is_refused(torch):
     from paper_1712_02443_amd import AimError
     wl = make_workload(0)
