@@ -131,6 +131,9 @@ typedef struct {
   int32_t fft_register;  /* 1 four-step passes of in-register DFTs (where compiled), 0 radix stages */
   int32_t near_block[2]; /* near field on the matrix cores, [AIM_FP64, AIM_MIXED]: blocks of 16
                             elements per workgroup, 1 or 2 (two share every coefficient load) */
+  int32_t near_fork[2];  /* where the near field leaves the caller's stream for the op's second
+                            stream, [AIM_FP64, AIM_MIXED]: 0 after the macromodel product, 1 after
+                            the projection, 2 after the y FFT pass (-1 keeps the current value) */
 } aim_tuning;
 
 /* Current launch configuration of the op. */

@@ -99,11 +99,13 @@ class AimOperator:
         check(self.lib.aim_get_tuning(self._op, ctypes.byref(t)))
         return {"fft_b": [int(t.fft_b[0]), int(t.fft_b[1])], "interp_tile": [int(t.interp_tx), int(t.interp_ty)],
                 "gemm_bf16": int(t.gemm_bf16), "fft_register": int(t.fft_register),
-                "near_block": [int(t.near_block[0]), int(t.near_block[1])]}
+                "near_block": [int(t.near_block[0]), int(t.near_block[1])],
+                "near_fork": [int(t.near_fork[0]), int(t.near_fork[1])]}
 
-    def set_tuning(self, fft_b=(0, 0), interp_tile=(0, 0), gemm_bf16=-1, fft_register=-1, near_block=(0, 0)):
+    def set_tuning(self, fft_b=(0, 0), interp_tile=(0, 0), gemm_bf16=-1, fft_register=-1, near_block=(0, 0),
+                   near_fork=(-1, -1)):
         t = _lib.AimTuning((ctypes.c_int32 * 2)(*fft_b), int(interp_tile[0]), int(interp_tile[1]), int(gemm_bf16),
-                           int(fft_register), (ctypes.c_int32 * 2)(*near_block))
+                           int(fft_register), (ctypes.c_int32 * 2)(*near_block), (ctypes.c_int32 * 2)(*near_fork))
         check(self.lib.aim_set_tuning(self._op, ctypes.byref(t)))
 
     def set_elem_type(self, elem_type, stream=None):

@@ -47,7 +47,7 @@ class AimInfo(ctypes.Structure):
 class AimTuning(ctypes.Structure):
     _fields_ = [("fft_b", ctypes.c_int32 * 2), ("interp_tx", ctypes.c_int32), ("interp_ty", ctypes.c_int32),
                 ("gemm_bf16", ctypes.c_int32), ("fft_register", ctypes.c_int32),
-                ("near_block", ctypes.c_int32 * 2)]
+                ("near_block", ctypes.c_int32 * 2), ("near_fork", ctypes.c_int32 * 2)]
 
 
 class GmresOpts(ctypes.Structure):

@@ -1,6 +1,7 @@
 """Autotuner of the product's launch configuration (aim_set_tuning): x-pass FFT line
-block, interpolation element tile, macromodel GEMM kernel, FFT pass kind and near-field
-element blocks per workgroup.
+block, interpolation element tile, macromodel GEMM kernel, FFT pass kind, near-field
+element blocks per workgroup and the point where the near field forks to the op's second
+stream.
 
 For one op, right-hand-side count and precision it times every admissible candidate
 with HIP events around back-to-back products, keeps only candidates whose product
@@ -46,14 +47,17 @@ def _candidates(op, precision):
     gemm = [cur["gemm_bf16"]] if precision == AIM_FP64 else ([0, 1] if inf["n_rwg"] % 8 == 0 else [0])
     fftk = [0, 1] if cur["fft_register"] or (inf["paths"] & 1) else [0]
     for b, t, g, f, nb in itertools.product(fft_b, tiles, gemm, fftk, (1, 2)):
-        yield {"fft_b": b, "interp_tile": list(t), "gemm_bf16": g, "fft_register": f, "near_block": nb}
+        yield {"fft_b": b, "interp_tile": list(t), "gemm_bf16": g, "fft_register": f, "near_block": nb,
+               "near_fork": 0}
 
 
 def _apply(op, cand, precision):
     fb = [cand["fft_b"], 0] if precision == AIM_FP64 else [0, cand["fft_b"]]
     nb = cand.get("near_block", 0)
+    nf = cand.get("near_fork", 0)
     op.set_tuning(fft_b=fb, interp_tile=cand["interp_tile"], gemm_bf16=cand["gemm_bf16"],
-                  fft_register=cand["fft_register"], near_block=[nb, 0] if precision == AIM_FP64 else [0, nb])
+                  fft_register=cand["fft_register"], near_block=[nb, 0] if precision == AIM_FP64 else [0, nb],
+                  near_fork=[nf, -1] if precision == AIM_FP64 else [-1, nf])
 
 
 def tune(op, nrhs: int = 1, precision: int = AIM_MIXED, cache_path: str | None = DEFAULT_CACHE, reps: int = 10,
@@ -93,23 +97,33 @@ def tune(op, nrhs: int = 1, precision: int = AIM_MIXED, cache_path: str | None =
 
     start_us = timed()
     best, results, rejected = None, [], 0
-    for cand in _candidates(op, precision):
+
+    def trial(cand):
+        nonlocal best, rejected
         try:
             _apply(op, cand, precision)
         except AimError:
-            continue
+            return
         op.matvec(x, precision=precision, out=y)
         err = float(np.abs(y.cpu().numpy() - ref).max() / scale)
         if not err <= tol:
             rejected += 1
-            continue
+            return
         us = timed()
         results.append((us, cand, err))
         if best is None or us < best[0]:
             best = (us, cand, err)
+
+    for cand in _candidates(op, precision):
+        trial(cand)
+    if best is not None:  # the fork point, on the best configuration of the kernels
+        base = best[1]
+        for nf in (1, 2):
+            trial(dict(base, near_fork=nf))
     if best is None:
         op.set_tuning(fft_b=start["fft_b"], interp_tile=start["interp_tile"], gemm_bf16=start["gemm_bf16"],
-                      fft_register=start["fft_register"], near_block=start["near_block"])
+                      fft_register=start["fft_register"], near_block=start["near_block"],
+                      near_fork=start["near_fork"])
         raise RuntimeError("no candidate launch configuration passed the accuracy check")
     _apply(op, best[1], precision)
     if cache_path:

@@ -329,15 +329,31 @@ int matvec_impl(aim_op* op, const cplx<T>* x, cplx<T>* y, int R, int flags, hipS
   if (op->near_mfma) na.grp_A = P.grpA;
   na.eb = op->near_eb[sizeof(T) == sizeof(double) ? 0 : 1];
   const bool fork = !ev && op->s_aux && flags != AIM_FAR_ONLY;
-  if (fork) {
-    AIM_HIP(hipEventRecord(op->ev_fork, s));
-    AIM_HIP(hipStreamWaitEvent(op->s_aux, op->ev_fork, 0));
-    AIM_HIP(launch_near<T>(uT, nf, na, P.near, op->s_aux));
-    AIM_HIP(hipEventRecord(op->ev_join, op->s_aux));
-  }
+  // the near field leaves the caller's stream at fork point fp (0 after the macromodel
+  // product, 1 after the projection, 2 after the y pass), so that it overlaps the kernels
+  // that follow; the results do not depend on the point
+  const int fp = fork ? op->near_fork[sizeof(T) == sizeof(double) ? 0 : 1] : -1;
+  auto fork_near = [&]() -> hipError_t {
+    hipError_t e = hipEventRecord(op->ev_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(op->s_aux, op->ev_fork, 0);
+    if (e == hipSuccess) e = launch_near<T>(uT, nf, na, P.near, op->s_aux);
+    if (e == hipSuccess) e = hipEventRecord(op->ev_join, op->s_aux);
+    return e;
+  };
+  if (fp == 0) AIM_HIP(fork_near());
   AIM_HIP(launch_project<T>(uT, grid, proj_args(op, R), P.Wp, s));
   if (ev) AIM_HIP(hipEventRecord(ev[2], s));
-  AIM_HIP(launch_convolve<T>(grid, grid, S, conv_args(op, P, R), s, ev ? ev + 3 : nullptr));
+  if (fp <= 1) {
+    if (fp == 1) AIM_HIP(fork_near());
+    AIM_HIP(launch_convolve<T>(grid, grid, S, conv_args(op, P, R), s, ev ? ev + 3 : nullptr));
+  } else {
+    ConvArgs ca = conv_args(op, P, R);
+    ca.passes = 1;  // y pass
+    AIM_HIP(launch_convolve<T>(grid, grid, S, ca, s, nullptr));
+    AIM_HIP(fork_near());
+    ca.passes = 2 | 4;  // x pass with the spectrum product, inverse y pass
+    AIM_HIP(launch_convolve<T>(grid, grid, S, ca, s, nullptr));
+  }
   if (ev) AIM_HIP(hipEventRecord(ev[5], s));
   if (fork)
     AIM_HIP(hipStreamWaitEvent(s, op->ev_join, 0));
@@ -666,6 +682,8 @@ int aim_get_tuning(const aim_op* op, aim_tuning* t) {
   t->fft_register = op->fft4 ? 1 : 0;
   t->near_block[0] = op->near_eb[0];
   t->near_block[1] = op->near_eb[1];
+  t->near_fork[0] = op->near_fork[0];
+  t->near_fork[1] = op->near_fork[1];
   return AIM_OK;
 }
 
@@ -717,6 +735,12 @@ int aim_set_tuning(aim_op* op, const aim_tuning* t) {
       set_error("tuning: near_block must be 1 or 2 element blocks per workgroup (0 keeps the current value)");
       return AIM_EINVAL;
     }
+  for (int p = 0; p < 2; ++p)
+    if (t->near_fork[p] < -1 || t->near_fork[p] > 2) {
+      set_error("tuning: near_fork must be 0 (after the GEMM), 1 (after the projection) or 2 (after the y pass); "
+                "-1 keeps the current value");
+      return AIM_EINVAL;
+    }
   if (t->gemm_bf16 == 1 && op->N % 8 != 0) {
     set_error("tuning: the split-BF16 product needs N % 8 == 0");
     return AIM_EINVAL;
@@ -731,6 +755,8 @@ int aim_set_tuning(aim_op* op, const aim_tuning* t) {
   if (t->fft_register >= 0) op->fft4 = t->fft_register == 1;
   for (int p = 0; p < 2; ++p)
     if (t->near_block[p] > 0) op->near_eb[p] = t->near_block[p];
+  for (int p = 0; p < 2; ++p)
+    if (t->near_fork[p] >= 0) op->near_fork[p] = t->near_fork[p];
   ++op->graph_epoch;  // captured GMRES iterations carry the old launch arguments
   return AIM_OK;
 }

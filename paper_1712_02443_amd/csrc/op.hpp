@@ -143,6 +143,7 @@ struct aim_op {
   void* Mb = nullptr;      // [n_types][6 planes][Krows / 8][N][8] bf16
   int interp_tx = 0, interp_ty = 0;  // interpolation tile (0 = automatic)
   int near_eb[2] = {1, 1};  // near field: blocks of 16 elements per workgroup [FP64, mixed]
+  int near_fork[2] = {0, 0};  // near field forked after: 0 the GEMM, 1 the projection, 2 the y pass [FP64, mixed]
   int *nbr = nullptr, *d_colT = nullptr, *rev_x = nullptr, *rev_y = nullptr, *col_list = nullptr;
   aimm::PrecData<double> p64;
   aimm::PrecData<float> p32;

@@ -85,7 +85,7 @@ def test_invalid_tuning_is_refused(torch):
     inf = op.info()
     bad_b = next(b for b in range(2, 50) if inf["ly"] % b)
     for kw in (dict(fft_b=(bad_b, 0)), dict(interp_tile=(3, 2)), dict(fft_b=(0, -1)), dict(near_block=(3, 0)),
-               dict(near_block=(0, -1))):
+               dict(near_block=(0, -1)), dict(near_fork=(3, -1)), dict(near_fork=(-1, -2))):
         with pytest.raises(AimError):
             op.set_tuning(**kw)
         assert op.tuning() == before
@@ -127,16 +127,19 @@ def test_every_accepted_line_block_launches(torch, idx):
 @pytest.mark.parametrize("idx", [0, 4])
 def test_near_blocks_give_identical_products(torch, idx):
     """One or two blocks of 16 elements per near-field workgroup do the same sums per
-    element in the same order: the products are bit-identical, in both precisions, on a
-    2 x 2 array and on a ragged 5 x 3 slice of the two-kind 648-RWG array."""
+    element in the same order, and the fork point of the near field's stream only moves
+    when it runs: the products are bit-identical, in both precisions, on a 2 x 2 array
+    and on a ragged 5 x 3 slice of the two-kind 648-RWG array."""
     wl = make_workload(idx, px=5, py=3, nrhs=2) if idx == 4 else make_workload(idx)
     op = make(wl)
     X = torch.from_numpy(wl.test_vectors(wl.nrhs)).to("cuda")
     for prec, x in ((0, X), (1, X.to(torch.complex64))):
         ys = []
         for nb in (1, 2):
-            op.set_tuning(near_block=(nb, nb))
-            assert op.tuning()["near_block"] == [nb, nb]
-            ys.append(op.matvec(x, precision=prec).cpu().numpy())
-        assert np.array_equal(ys[0], ys[1]), f"precision {prec}: max diff {np.abs(ys[0] - ys[1]).max()}"
+            for fork in (0, 1, 2):
+                op.set_tuning(near_block=(nb, nb), near_fork=(fork, fork))
+                assert op.tuning()["near_block"] == [nb, nb] and op.tuning()["near_fork"] == [fork, fork]
+                ys.append(op.matvec(x, precision=prec).cpu().numpy())
+        for y in ys[1:]:
+            assert np.array_equal(ys[0], y), f"precision {prec}: max diff {np.abs(ys[0] - y).max()}"
     op.close()

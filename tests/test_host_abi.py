@@ -159,16 +159,16 @@ def test_device_calls_on_host_op_report_state(lib):
 def test_tuning_calls_check_their_arguments(lib):
     """aim_get_tuning / aim_set_tuning: null arguments are refused, a host-only op reports
     its build-time configuration and refuses a new one (it has no device kernels), and
-    the Python struct has the layout the header declares (8 int32 fields)."""
+    the Python struct has the layout the header declares (10 int32 fields)."""
     from paper_1712_02443_amd import _lib
-    assert ctypes.sizeof(_lib.AimTuning) == 8 * 4
+    assert ctypes.sizeof(_lib.AimTuning) == 10 * 4
     wl = make_workload(0)
     op = _host_op(wl)
     t = _lib.AimTuning()
     assert lib.aim_get_tuning(None, ctypes.byref(t)) == _lib.AIM_EINVAL
     assert lib.aim_get_tuning(op._op, None) == _lib.AIM_EINVAL
     assert lib.aim_get_tuning(op._op, ctypes.byref(t)) == _lib.AIM_OK
-    assert list(t.near_block) == [1, 1] and t.interp_tx >= 1 and t.interp_ty >= 1
+    assert list(t.near_block) == [1, 1] and list(t.near_fork) == [0, 0] and t.interp_tx >= 1 and t.interp_ty >= 1
     assert lib.aim_set_tuning(None, ctypes.byref(t)) == _lib.AIM_EINVAL
     assert lib.aim_set_tuning(op._op, ctypes.byref(t)) == _lib.AIM_ESTATE
     assert b"host-only" in lib.aim_last_error()
